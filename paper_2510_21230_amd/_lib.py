@@ -1,0 +1,230 @@
+"""ctypes binding of libatm3.so (argument marshalling only).
+
+Every step of the computation runs in the HIP kernels of libatm3.so; this
+module only passes torch device pointers, sizes and the current HIP stream
+across the C ABI declared in include/atm3.h, and turns status codes into
+exceptions.  If the library is missing it raises: there is no other path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libatm3.so")
+
+ATM3_OK = 0
+ATM3_EINVAL = -1
+ATM3_EDEVICE = -2
+ATM3_ENOMEM = -3
+ATM3_ERANGE = -4
+ATM3_EOVERFLOW = -5
+
+TRUNCATIONS = {"pair": 0, "product": 1}
+VARIANTS = {"3c08": 0, "3c18": 1, "3c01": 2}
+TERM_LJ = 1
+TERM_ATM = 2
+
+EXPORTS = (
+    "atm3_create", "atm3_destroy", "atm3_set_stream", "atm3_last_error", "atm3_version",
+    "atm3_bin_cells", "atm3_compute_forces", "atm3_compute_forces_async",
+)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("sigma", ctypes.c_double), ("nu", ctypes.c_double),
+                ("rc", ctypes.c_double), ("truncation", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("terms", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("e_lj", ctypes.c_double), ("e_atm", ctypes.c_double), ("w_lj", ctypes.c_double),
+                ("w_atm", ctypes.c_double), ("n_pairs", ctypes.c_int64), ("n_triplets", ctypes.c_int64),
+                ("n_candidates", ctypes.c_int64), ("ncell", ctypes.c_int32 * 3), ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"e_lj": self.e_lj, "e_atm": self.e_atm, "w_lj": self.w_lj, "w_atm": self.w_atm,
+                "n_pairs": int(self.n_pairs), "n_triplets": int(self.n_triplets),
+                "n_candidates": int(self.n_candidates), "ncell": tuple(self.ncell),
+                "status": int(self.status)}
+
+
+class Atm3Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"atm3 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load():
+    """Load libatm3.so (raises ImportError if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_2510_21230_amd.build")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        dptr = ctypes.POINTER(ctypes.c_double)
+        iptr = ctypes.POINTER(ctypes.c_int32)
+        lib.atm3_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        lib.atm3_create.restype = ctypes.c_int
+        lib.atm3_destroy.argtypes = [vp]
+        lib.atm3_destroy.restype = None
+        lib.atm3_set_stream.argtypes = [vp, vp]
+        lib.atm3_set_stream.restype = ctypes.c_int
+        lib.atm3_last_error.argtypes = [vp]
+        lib.atm3_last_error.restype = ctypes.c_char_p
+        lib.atm3_version.argtypes = []
+        lib.atm3_version.restype = ctypes.c_char_p
+        lib.atm3_bin_cells.argtypes = [vp, vp, i64, dptr, ctypes.c_double, vp, vp, vp, iptr]
+        lib.atm3_bin_cells.restype = ctypes.c_int
+        lib.atm3_compute_forces.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), vp, ctypes.POINTER(Result)]
+        lib.atm3_compute_forces.restype = ctypes.c_int
+        lib.atm3_compute_forces_async.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), vp, vp]
+        lib.atm3_compute_forces_async.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def _box(box):
+    b = [float(v) for v in (box if hasattr(box, "__len__") else (box, box, box))]
+    if len(b) != 3:
+        raise ValueError("box must have 3 lengths")
+    return (ctypes.c_double * 3)(*b)
+
+
+def make_params(rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair", variant="3c08",
+                terms=TERM_LJ | TERM_ATM, check_finite=False) -> Params:
+    return Params(float(eps), float(sigma), float(nu), float(rc), TRUNCATIONS[truncation],
+                  VARIANTS[variant], int(terms), 2 if check_finite else 0)
+
+
+class Context:
+    """One libatm3 context (device scratch owner) on a torch CUDA/HIP device."""
+
+    def __init__(self, device=None):
+        import torch
+        self.lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.atm3_create(ctypes.byref(h), self.device.index or 0)
+        if rc != ATM3_OK:
+            raise Atm3Error(rc, f"atm3_create failed for {self.device}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.atm3_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != ATM3_OK:
+            msg = self.lib.atm3_last_error(self.h).decode(errors="replace")
+            if rc == ATM3_EINVAL:
+                raise ValueError(msg)
+            raise Atm3Error(rc, msg)
+
+    def _stream(self):
+        import torch
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self._check(self.lib.atm3_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def _pos(self, pos):
+        import torch
+        if not (pos.is_cuda and pos.dtype == torch.float64 and pos.dim() == 2 and pos.shape[1] == 3):
+            raise ValueError("pos must be a (N,3) float64 tensor on the GPU")
+        if pos.device != self.device:
+            raise ValueError(f"pos is on {pos.device}, context on {self.device}")
+        return pos.contiguous()
+
+    def bin_cells(self, pos, box, rc):
+        """Cell of each molecule, cell_start, perm (sorted slot -> input index), ncell."""
+        import torch
+        pos = self._pos(pos)
+        b = _box(box)
+        nc = (ctypes.c_int32 * 3)()
+        self._check(self.lib.atm3_bin_cells(self.h, None, 0, b, float(rc), None, None, None, nc))
+        ncells = nc[0] * nc[1] * nc[2]
+        n = pos.shape[0]
+        cell_of = torch.empty(n, dtype=torch.int32, device=self.device)
+        start = torch.empty(ncells + 1, dtype=torch.int32, device=self.device)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._stream()
+        self._check(self.lib.atm3_bin_cells(self.h, ctypes.c_void_p(pos.data_ptr()), n, b, float(rc),
+                                            ctypes.c_void_p(cell_of.data_ptr()),
+                                            ctypes.c_void_p(start.data_ptr()),
+                                            ctypes.c_void_p(perm.data_ptr()), nc))
+        return cell_of, start, perm, tuple(nc)
+
+    def compute_forces(self, pos, box, forces=None, **kw):
+        """Forces (N,3) float32 in input order and the result dict; blocks."""
+        import torch
+        pos = self._pos(pos)
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+        p = make_params(**kw)
+        r = Result()
+        self._stream()
+        self._check(self.lib.atm3_compute_forces(self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box),
+                                                 ctypes.byref(p), ctypes.c_void_p(forces.data_ptr()),
+                                                 ctypes.byref(r)))
+        return forces, r.as_dict()
+
+    def compute_forces_async(self, pos, box, forces, result_dev, params: Params):
+        """Enqueue one evaluation on the current stream; result_dev is a device
+        tensor of at least sizeof(atm3_result) bytes."""
+        n = pos.shape[0]
+        self._stream()
+        self._check(self.lib.atm3_compute_forces_async(
+            self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box), ctypes.byref(params),
+            ctypes.c_void_p(forces.data_ptr()), ctypes.c_void_p(result_dev.data_ptr())))
+
+
+def result_from_bytes(buf: bytes) -> dict:
+    """Decode a device result (copied to host bytes) into a dict."""
+    r = Result.from_buffer_copy(buf[:ctypes.sizeof(Result)])
+    return r.as_dict()
+
+
+_ctxs = {}
+
+
+def context(device=None) -> Context:
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    key = torch.device("cuda", device).index if isinstance(device, int) else torch.device(device).index
+    if key not in _ctxs:
+        _ctxs[key] = Context(key)
+    return _ctxs[key]
+
+
+def bin_cells(pos, box, rc=2.5):
+    return context(pos.device).bin_cells(pos, box, rc)
+
+
+def compute_forces(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
+                   variant="3c08", terms=TERM_LJ | TERM_ATM, check_finite=False, forces=None):
+    """Linked-cell LJ + ATM forces of a periodic system on the GPU.
+
+    Returns (forces[N,3] float32, result dict with e_lj, e_atm, w_lj, w_atm,
+    n_pairs, n_triplets, n_candidates, ncell)."""
+    return context(pos.device).compute_forces(pos, box, forces=forces, rc=rc, nu=nu, eps=eps, sigma=sigma,
+                                              truncation=truncation, variant=variant, terms=terms,
+                                              check_finite=check_finite)

@@ -1,0 +1,228 @@
+// C ABI of libatm3.so: context, scratch ownership, argument checks, launches.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "atm3_internal.h"
+
+namespace atm3 {
+
+int fail(atm3_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(atm3_ctx* ctx, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(ctx, e == hipErrorOutOfMemory ? ATM3_ENOMEM : ATM3_EDEVICE, m);
+}
+
+int ensure(atm3_ctx* ctx, Buf b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (ctx->s.cap[b] >= bytes) return ATM3_OK;
+  if (ctx->s.p[b]) {
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+    (void)hipFree(ctx->s.p[b]);
+    ctx->s.p[b] = nullptr;
+    ctx->s.cap[b] = 0;
+  }
+  size_t want = bytes + bytes / 8;  // headroom for slightly larger inputs
+  hipError_t e = hipMalloc(&ctx->s.p[b], want);
+  if (e != hipSuccess) {
+    ctx->s.p[b] = nullptr;
+    return hip_fail(ctx, e, "hipMalloc (scratch)");
+  }
+  ctx->s.cap[b] = want;
+  return ATM3_OK;
+}
+
+bool make_grid(const double box[3], double rc, Grid* g) {
+  int64_t total = 1;
+  for (int d = 0; d < 3; ++d) {
+    double q = floor(box[d] / rc);
+    if (!(q >= 1.0) || q > 1.0e6) return false;
+    g->n[d] = (int32_t)q;
+    g->box[d] = box[d];
+    g->inv[d] = (double)g->n[d] / box[d];
+    g->side[d] = box[d] / (double)g->n[d];
+    total *= g->n[d];
+  }
+  if (total > (int64_t)1 << 30) return false;
+  g->ncells = total;
+  return true;
+}
+
+}  // namespace atm3
+
+using namespace atm3;
+
+namespace {
+
+int set_device(atm3_ctx* ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  return ATM3_OK;
+}
+
+int check_box(atm3_ctx* ctx, const double* box, double rc) {
+  if (!box) return fail(ctx, ATM3_EINVAL, "box is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0) || !isfinite(box[d])) return fail(ctx, ATM3_EINVAL, "box lengths must be finite and > 0");
+  if (!(rc > 0.0) || !isfinite(rc)) return fail(ctx, ATM3_EINVAL, "rc must be finite and > 0");
+  return ATM3_OK;
+}
+
+int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, const atm3_params* p, Grid* g) {
+  if (!ctx) return ATM3_EINVAL;
+  ctx->err.clear();
+  if (!p) return fail(ctx, ATM3_EINVAL, "params is NULL");
+  if (!pos) return fail(ctx, ATM3_EINVAL, "pos is NULL");
+  if (n < 1 || n > (int64_t)0x7fffffff / 3) return fail(ctx, ATM3_EINVAL, "n must be in [1, 2^31/3)");
+  int rc = check_box(ctx, box, p->rc);
+  if (rc) return rc;
+  if (!(p->sigma > 0.0) || !isfinite(p->sigma)) return fail(ctx, ATM3_EINVAL, "sigma must be finite and > 0");
+  if (!isfinite(p->eps) || !isfinite(p->nu)) return fail(ctx, ATM3_EINVAL, "eps and nu must be finite");
+  if (p->truncation != ATM3_TRUNC_PAIR && p->truncation != ATM3_TRUNC_PRODUCT)
+    return fail(ctx, ATM3_EINVAL, "truncation must be ATM3_TRUNC_PAIR or ATM3_TRUNC_PRODUCT");
+  if (p->variant < ATM3_VARIANT_3C08 || p->variant > ATM3_VARIANT_3C01)
+    return fail(ctx, ATM3_EINVAL, "variant must be 3c08, 3c18 or 3c01");
+  if (p->terms < 1 || p->terms > 3) return fail(ctx, ATM3_EINVAL, "terms must be a non-empty OR of ATM3_TERM_*");
+  if (p->truncation != ATM3_TRUNC_PAIR || p->variant != ATM3_VARIANT_3C08)
+    return fail(ctx, ATM3_EINVAL, "only the pairwise cutoff with the 3c08 cell sets is implemented");
+  if (!make_grid(box, p->rc, g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range (floor(L/rc) < 1 or too many cells)");
+  int need = 3;
+  if (p->truncation == ATM3_TRUNC_PRODUCT) need = (p->variant == ATM3_VARIANT_3C08) ? 5 : 7;
+  for (int d = 0; d < 3; ++d)
+    if (g->n[d] < need)
+      return fail(ctx, ATM3_EINVAL,
+                  "box too small: floor(L/rc) = " + std::to_string(g->n[d]) + " < " + std::to_string(need) +
+                      " cells in some dimension");
+  int r = set_device(ctx);
+  if (r) return r;
+  const size_t N = (size_t)n, C = (size_t)g->ncells;
+  if ((r = ensure(ctx, B_CELL_OF, 4 * N))) return r;
+  if ((r = ensure(ctx, B_RANK, 4 * N))) return r;
+  if ((r = ensure(ctx, B_COUNT, 4 * C))) return r;
+  if ((r = ensure(ctx, B_START, 4 * (C + 1)))) return r;
+  if ((r = ensure(ctx, B_PERM, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SORTED, 32 * N))) return r;
+  if ((r = ensure(ctx, B_FPART, 8 * 24 * N))) return r;
+  if ((r = ensure(ctx, B_BLKD, 8 * 3 * C))) return r;
+  if ((r = ensure(ctx, B_BLKI, 4 * 2 * C))) return r;
+  if ((r = ensure(ctx, B_DEFER, 4 * (C + 2)))) return r;
+  return ATM3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* atm3_version(void) { return "atm3 0.1 (gfx950)"; }
+
+int atm3_create(atm3_ctx** out, int device_ordinal) {
+  if (!out) return ATM3_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device_ordinal < 0 || device_ordinal >= count)
+    return ATM3_EDEVICE;
+  atm3_ctx* ctx = new (std::nothrow) atm3_ctx();
+  if (!ctx) return ATM3_ENOMEM;
+  ctx->device = device_ordinal;
+  if (hipSetDevice(device_ordinal) != hipSuccess) {
+    delete ctx;
+    return ATM3_EDEVICE;
+  }
+  if (hipMalloc(&ctx->dres, sizeof(atm3_result)) != hipSuccess) {
+    delete ctx;
+    return ATM3_ENOMEM;
+  }
+  if (hipHostMalloc(&ctx->hres, sizeof(atm3_result), hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(ctx->dres);
+    delete ctx;
+    return ATM3_ENOMEM;
+  }
+  *out = ctx;
+  return ATM3_OK;
+}
+
+void atm3_destroy(atm3_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (int b = 0; b < B_NBUF; ++b)
+    if (ctx->s.p[b]) (void)hipFree(ctx->s.p[b]);
+  if (ctx->dres) (void)hipFree(ctx->dres);
+  if (ctx->hres) (void)hipHostFree(ctx->hres);
+  delete ctx;
+}
+
+int atm3_set_stream(atm3_ctx* ctx, void* hip_stream) {
+  if (!ctx) return ATM3_EINVAL;
+  ctx->stream = (hipStream_t)hip_stream;
+  return ATM3_OK;
+}
+
+const char* atm3_last_error(const atm3_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], double rc, int32_t* cell_of,
+                   int32_t* cell_start, int32_t* perm, int32_t ncell_out[3]) {
+  if (!ctx) return ATM3_EINVAL;
+  ctx->err.clear();
+  int r = check_box(ctx, box, rc);
+  if (r) return r;
+  Grid g;
+  if (!make_grid(box, rc, &g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range");
+  if (ncell_out)
+    for (int d = 0; d < 3; ++d) ncell_out[d] = g.n[d];
+  if (!cell_start) return ATM3_OK;
+  if (!pos || !cell_of || !perm) return fail(ctx, ATM3_EINVAL, "NULL device pointer");
+  if (n < 1 || n > (int64_t)0x7fffffff / 3) return fail(ctx, ATM3_EINVAL, "n must be in [1, 2^31/3)");
+  if ((r = set_device(ctx))) return r;
+  const size_t N = (size_t)n, C = (size_t)g.ncells;
+  if ((r = ensure(ctx, B_CELL_OF, 4 * N))) return r;
+  if ((r = ensure(ctx, B_RANK, 4 * N))) return r;
+  if ((r = ensure(ctx, B_COUNT, 4 * C))) return r;
+  if ((r = ensure(ctx, B_START, 4 * (C + 1)))) return r;
+  if ((r = ensure(ctx, B_PERM, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SORTED, 32 * N))) return r;
+  hipError_t e = launch_binning(ctx, pos, n, g);
+  if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
+  e = hipMemcpyAsync(cell_of, ctx->s.p[B_CELL_OF], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(cell_start, ctx->s.p[B_START], 4 * (C + 1), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(perm, ctx->s.p[B_PERM], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
+  return ATM3_OK;
+}
+
+int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
+                              const atm3_params* params, float* forces, atm3_result* out_dev) {
+  Grid g;
+  int r = prepare(ctx, pos, n, box, params, &g);
+  if (r) return r;
+  if (!forces || !out_dev) return fail(ctx, ATM3_EINVAL, "forces / result pointer is NULL");
+  hipError_t e = launch_binning(ctx, pos, n, g);
+  if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
+  e = launch_forces(ctx, pos, n, g, *params, forces, out_dev);
+  if (e != hipSuccess) return hip_fail(ctx, e, "force launch");
+  return ATM3_OK;
+}
+
+int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], const atm3_params* params,
+                        float* forces, atm3_result* out) {
+  if (!out) return fail(ctx, ATM3_EINVAL, "result pointer is NULL");
+  int r = atm3_compute_forces_async(ctx, pos, n, box, params, forces, ctx ? ctx->dres : nullptr);
+  if (r) return r;
+  hipError_t e = hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(atm3_result), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "result copy");
+  *out = *ctx->hres;
+  if (out->status != ATM3_OK)
+    return fail(ctx, out->status, "a 2x2x2 block of cells holds more than 512 molecules");
+  return ATM3_OK;
+}
+
+}  // extern "C"

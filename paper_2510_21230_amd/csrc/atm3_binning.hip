@@ -1,0 +1,156 @@
+// Linked-cell binning on gfx950: wrap + cell index in FP64 (bit-exact, no
+// contraction), counting sort into cell order, stable within each cell, and
+// the gather of cell-centred FP64 coordinates the force kernels stage in LDS.
+//
+// Paper, Sec. 4 (preamble): cells are ordered lexicographically and the cell
+// side equals (here: is at least) the cutoff radius.  The cell of a molecule
+// is floor(x * n/L) of its wrapped coordinate, clamped to [0, n-1].
+//
+// This translation unit is compiled with -ffp-contract=off; the pragma below
+// states the same requirement in the source.
+#pragma clang fp contract(off)
+
+#include "atm3_internal.h"
+
+namespace atm3 {
+namespace {
+
+struct BinArgs {
+  int32_t n[3];
+  double box[3];
+  double inv[3];
+  double side[3];
+};
+
+// x <- x - L*floor(x/L); c = clamp(floor(x * inv), 0, n-1).
+__device__ __forceinline__ int cell_coord(double x, double L, double inv, int n, double* xw) {
+  double f = floor(x / L);
+  double w = x - L * f;
+  double t = floor(w * inv);
+  int c = (t < 0.0) ? 0 : (t > (double)(n - 1) ? n - 1 : (int)t);
+  *xw = w;
+  return c;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < count; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// One thread per molecule: linear cell and arrival rank within the cell.
+__global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ pos, int32_t n, BinArgs g,
+                                                   int32_t* __restrict__ cell_of, int32_t* __restrict__ rank,
+                                                   int32_t* __restrict__ count) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double w;
+  int cx = cell_coord(pos[3 * (int64_t)i + 0], g.box[0], g.inv[0], g.n[0], &w);
+  int cy = cell_coord(pos[3 * (int64_t)i + 1], g.box[1], g.inv[1], g.n[1], &w);
+  int cz = cell_coord(pos[3 * (int64_t)i + 2], g.box[2], g.inv[2], g.n[2], &w);
+  int32_t c = (cz * g.n[1] + cy) * g.n[0] + cx;
+  cell_of[i] = c;
+  rank[i] = atomicAdd(&count[c], 1);
+}
+
+// Exclusive prefix over the cell counts, one workgroup of 1024 threads:
+// each thread sums a contiguous chunk, the chunk sums are scanned in LDS.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t* __restrict__ start,
+                                               int64_t ncells) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (ncells + 1023) / 1024;
+  const int64_t lo = (int64_t)t * per;
+  const int64_t hi = lo + per < ncells ? lo + per : ncells;
+  int32_t s = 0;
+  for (int64_t k = lo; k < hi; ++k) s += count[k];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int32_t v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = (t == 0) ? 0 : part[t - 1];
+  for (int64_t k = lo; k < hi; ++k) {
+    start[k] = run;
+    run += count[k];
+  }
+  if (t == 1023) start[ncells] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
+                                                 const int32_t* __restrict__ start, int32_t n,
+                                                 int32_t* __restrict__ perm) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  perm[start[cell_of[i]] + rank[i]] = i;
+}
+
+// Restore input order inside each cell (atomic ranks arrive in any order):
+// insertion sort of the few entries of one cell per thread.
+__global__ __launch_bounds__(256) void k_cellsort(const int32_t* __restrict__ start, int64_t ncells,
+                                                  int32_t* __restrict__ perm) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncells) return;
+  const int32_t lo = start[c], hi = start[c + 1];
+  for (int32_t a = lo + 1; a < hi; ++a) {
+    int32_t v = perm[a];
+    int32_t b = a - 1;
+    while (b >= lo && perm[b] > v) {
+      perm[b + 1] = perm[b];
+      --b;
+    }
+    perm[b + 1] = v;
+  }
+}
+
+// One thread per sorted slot: FP64 coordinates relative to the centre of the
+// molecule's cell, x_wrapped - (c + 1/2) * side, and the input index in .w.
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ pos, const int32_t* __restrict__ perm,
+                                                int32_t n, BinArgs g, double4* __restrict__ sorted) {
+  int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int32_t i = perm[s];
+  double loc[3];
+  for (int d = 0; d < 3; ++d) {
+    double w;
+    int c = cell_coord(pos[3 * (int64_t)i + d], g.box[d], g.inv[d], g.n[d], &w);
+    double centre = ((double)c + 0.5) * g.side[d];
+    loc[d] = w - centre;
+  }
+  sorted[s] = make_double4(loc[0], loc[1], loc[2], (double)i);
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& gr) {
+  BinArgs g;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = gr.n[d];
+    g.box[d] = gr.box[d];
+    g.inv[d] = gr.inv[d];
+    g.side[d] = gr.side[d];
+  }
+  hipStream_t st = ctx->stream;
+  int32_t* cell_of = (int32_t*)ctx->s.p[B_CELL_OF];
+  int32_t* rank = (int32_t*)ctx->s.p[B_RANK];
+  int32_t* count = (int32_t*)ctx->s.p[B_COUNT];
+  int32_t* start = (int32_t*)ctx->s.p[B_START];
+  int32_t* perm = (int32_t*)ctx->s.p[B_PERM];
+  double4* sorted = (double4*)ctx->s.p[B_SORTED];
+  const int32_t nn = (int32_t)n;
+  unsigned fb = blocks_for(gr.ncells, 256);
+  if (fb > 4096) fb = 4096;
+  hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, count, gr.ncells, 0);
+  hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, nn, g, cell_of, rank, count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, start, gr.ncells);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, cell_of, rank, start, nn, perm);
+  hipLaunchKernelGGL(k_cellsort, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, gr.ncells, perm);
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, nn, g, sorted);
+  return hipGetLastError();
+}
+
+}  // namespace atm3

@@ -1,0 +1,72 @@
+// Internal declarations shared by the translation units of libatm3.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "atm3.h"
+
+namespace atm3 {
+
+// Grid of linked cells and the FP64 constants every binning step uses.
+struct Grid {
+  int32_t n[3];     // cells per dimension, floor(L_d / rc)
+  int64_t ncells;   // n[0]*n[1]*n[2]
+  double box[3];    // L_d
+  double inv[3];    // n_d / L_d  (FP64, correctly rounded on host and device)
+  double side[3];   // L_d / n_d
+};
+
+// Device scratch of one evaluation, owned by the context (grow-only).
+enum Buf {
+  B_CELL_OF = 0,  // int32 [N]   linear cell per molecule (input order)
+  B_RANK,         // int32 [N]   arrival rank within the cell (unstable)
+  B_COUNT,        // int32 [C]   molecules per cell
+  B_START,        // int32 [C+1] exclusive prefix of counts
+  B_PERM,         // int32 [N]   sorted slot -> input index (stable)
+  B_SORTED,       // double4[N]  cell-centred FP64 coordinates, .w = input index
+  B_FPART,        // double[8][3][N] per-corner partial forces (sorted order)
+  B_BLKD,         // double[C][3] per-block e_lj', w_lj', e_atm'
+  B_BLKI,         // int32 [C][2] per-block pair and triplet counts
+  B_DEFER,        // int32 [C+1] deferred (large) blocks; [0] = count
+  B_NBUF
+};
+
+struct Scratch {
+  void* p[B_NBUF] = {};
+  size_t cap[B_NBUF] = {};
+};
+
+}  // namespace atm3
+
+struct atm3_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  atm3::Scratch s;
+  atm3_result* dres = nullptr;  // device result of the synchronous path
+  atm3_result* hres = nullptr;  // pinned host copy
+};
+
+namespace atm3 {
+
+// Status helpers (set ctx->err and return the code).
+int fail(atm3_ctx* ctx, int code, const std::string& msg);
+int hip_fail(atm3_ctx* ctx, hipError_t e, const char* what);
+int ensure(atm3_ctx* ctx, Buf b, size_t bytes);
+
+// Grid from box and cutoff; returns false if any n_d < 1 or sizes overflow.
+bool make_grid(const double box[3], double rc, Grid* g);
+
+// Binning (atm3_binning.hip): fills B_CELL_OF, B_COUNT, B_START, B_PERM,
+// B_SORTED from the FP64 positions.
+hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g);
+
+// Forces (atm3_forces.hip): block kernels, per-corner partial forces, final
+// gather into `forces` and the reduction into `res_dev`.
+hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g,
+                         const atm3_params& p, float* forces, atm3_result* res_dev);
+
+}  // namespace atm3

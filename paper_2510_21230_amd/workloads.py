@@ -57,6 +57,43 @@ def uniform(n: int, box, seed: int = SEED_BASE + 7):
     return np.ascontiguousarray(rng.uniform(0.0, 1.0, size=(n, 3)) * box), box.copy()
 
 
+def rsa(n: int, box, dmin: float = 0.8, lo=None, hi=None, seed: int = SEED_BASE + 8,
+        max_tries: int = 200):
+    """Random sequential addition: n molecules uniform in the region [lo, hi)
+    of a periodic box, each at least dmin (minimum image) from all earlier
+    ones.  Returns (pos, box)."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    lo = np.zeros(3) if lo is None else np.asarray(lo, dtype=np.float64)
+    hi = box.copy() if hi is None else np.asarray(hi, dtype=np.float64)
+    g = np.maximum((box // dmin).astype(int), 1)
+    grid = {}
+    pts = []
+    d2min = dmin * dmin
+    for _ in range(n):
+        for _t in range(max_tries):
+            p = (lo + rng.uniform(0.0, 1.0, 3) * (hi - lo)) % box
+            c = tuple((p / box * g).astype(int) % g)
+            ok = True
+            for off in np.ndindex(3, 3, 3):
+                cc = tuple((np.array(c) + np.array(off) - 1) % g)
+                for q in grid.get(cc, ()):
+                    d = p - q
+                    d -= box * np.rint(d / box)
+                    if d @ d < d2min:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if ok:
+                grid.setdefault(c, []).append(p)
+                pts.append(p)
+                break
+        else:
+            raise RuntimeError("rsa: region too full for the requested n and dmin")
+    return np.ascontiguousarray(np.array(pts)), box.copy()
+
+
 def slab(lx=30.0, ly=30.0, lz=90.0, z0=30.0, width=30.0, rho_l=0.7, rho_v=0.02,
          jitter=0.05, seed: int = SEED_BASE + 3):
     """Liquid slab z in [z0, z0+width) on a jittered FCC lattice at rho_l,
