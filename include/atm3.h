@@ -41,7 +41,7 @@ extern "C" {
 #define ATM3_EINVAL (-1)    /* invalid argument (message says which)          */
 #define ATM3_EDEVICE (-2)   /* HIP runtime error or bad device ordinal        */
 #define ATM3_ENOMEM (-3)    /* device allocation failed                       */
-#define ATM3_ERANGE (-4)    /* non-finite position (when checking is enabled)  */
+#define ATM3_ERANGE (-4)    /* non-finite input, or a force beyond +-2^31     */
 #define ATM3_EOVERFLOW (-5) /* a 2x2x2 cell block holds more than 512 molecules */
 
 /* Truncation conditions of Sec. 2. */
@@ -131,7 +131,10 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
  * n_d >= 3, and n_d >= 5 for the product rule with 3c08, n_d >= 7 for the
  * product rule with 3c18 or 3c01 (so cell shifts equal minimum images).
  * Returns ATM3_EOVERFLOW if some 2x2x2 block of cells holds more than 512
- * molecules (forces are then undefined). */
+ * molecules, ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
+ * (forces are accumulated exactly in 64-bit fixed point with 2^-32
+ * resolution); forces are undefined in both cases.  Results are
+ * reproducible bit for bit between calls. */
 int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                         const atm3_params* params, float* forces, atm3_result* out);
 
@@ -141,6 +144,22 @@ int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const doubl
  * host before anything is enqueued. */
 int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                               const atm3_params* params, float* forces, atm3_result* out_dev);
+
+/* Kernel timing with HIP events recorded on the context stream around each
+ * phase of atm3_compute_forces[_async]:
+ *   ATM3_PHASE_BINNING  wrap/cell index, counting sort, coordinate gather
+ *   ATM3_PHASE_BLOCK    the fused LJ + ATM kernel over 2x2x2 cell blocks
+ *   ATM3_PHASE_BIG      the same for blocks of more than 128 molecules
+ *   ATM3_PHASE_REDUCE   per-molecule force gather and the global reduction
+ * atm3_profile_enable(ctx, 1) starts recording (and clears the totals);
+ * atm3_profile_read() waits for the stream, then returns the summed elapsed
+ * milliseconds and number of timed launches of one phase. */
+#define ATM3_PHASE_BINNING 0
+#define ATM3_PHASE_BLOCK 1
+#define ATM3_PHASE_BIG 2
+#define ATM3_PHASE_REDUCE 3
+int atm3_profile_enable(atm3_ctx* ctx, int enable);
+int atm3_profile_read(atm3_ctx* ctx, int phase, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

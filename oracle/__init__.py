@@ -85,6 +85,8 @@ def _load():
         lib.orc_triplet.restype = None
         lib.orc_visited.argtypes = [P(ctypes.c_int32)] * 4 + [ctypes.c_int]
         lib.orc_visited.restype = ctypes.c_int
+        lib.orc_threads.argtypes = []
+        lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -173,6 +175,11 @@ def molecules(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
     if rc_ != 0:
         raise ValueError("oracle: invalid arguments")
     return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(_load().orc_threads())
 
 
 def atm_energy(rij, rik, rjk, nu):

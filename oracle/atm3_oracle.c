@@ -568,6 +568,15 @@ int orc_molecules(const double* pos, int64_t n, const double box[3], const orc_p
   return 0;
 }
 
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* Single-triplet helpers for pinning tests: energy, the three force pairs and
  * the virial of one triplet given the three displacement vectors. */
 void orc_triplet(const double rij[3], const double rik[3], const double rjk[3], double nu,

@@ -29,7 +29,9 @@ TERM_ATM = 2
 EXPORTS = (
     "atm3_create", "atm3_destroy", "atm3_set_stream", "atm3_last_error", "atm3_version",
     "atm3_bin_cells", "atm3_compute_forces", "atm3_compute_forces_async",
+    "atm3_profile_enable", "atm3_profile_read",
 )
+PHASES = {"binning": 0, "block": 1, "big": 2, "reduce": 3}
 
 
 class Params(ctypes.Structure):
@@ -89,6 +91,11 @@ def load():
         lib.atm3_compute_forces.restype = ctypes.c_int
         lib.atm3_compute_forces_async.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), vp, vp]
         lib.atm3_compute_forces_async.restype = ctypes.c_int
+        lib.atm3_profile_enable.argtypes = [vp, ctypes.c_int]
+        lib.atm3_profile_enable.restype = ctypes.c_int
+        lib.atm3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_int64)]
+        lib.atm3_profile_read.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -194,6 +201,22 @@ class Context:
         self._check(self.lib.atm3_compute_forces_async(
             self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box), ctypes.byref(params),
             ctypes.c_void_p(forces.data_ptr()), ctypes.c_void_p(result_dev.data_ptr())))
+
+
+    def profile(self, enable: bool):
+        """Start (clearing totals) or stop HIP-event timing of the kernel phases."""
+        self._stream()
+        self._check(self.lib.atm3_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{phase: (total_ms, launches)} of the event-timed kernel phases."""
+        out = {}
+        for name, ph in PHASES.items():
+            ms = ctypes.c_double()
+            k = ctypes.c_int64()
+            self._check(self.lib.atm3_profile_read(self.h, ph, ctypes.byref(ms), ctypes.byref(k)))
+            out[name] = (ms.value, int(k.value))
+        return out
 
 
 def result_from_bytes(buf: bytes) -> dict:

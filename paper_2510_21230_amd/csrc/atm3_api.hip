@@ -39,6 +39,24 @@ int ensure(atm3_ctx* ctx, Buf b, size_t bytes) {
   return ATM3_OK;
 }
 
+static hipError_t phase_event(atm3_ctx* ctx, int phase, int which) {
+  if (!ctx->profile) return hipSuccess;
+  PhaseTimer& t = ctx->timer[phase];
+  const size_t k = 2 * t.used + (size_t)which;
+  while (t.ev.size() <= k) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    t.ev.push_back(e);
+  }
+  hipError_t err = hipEventRecord(t.ev[k], ctx->stream);
+  if (which == 1) ++t.used;
+  return err;
+}
+
+hipError_t phase_begin(atm3_ctx* ctx, int phase) { return phase_event(ctx, phase, 0); }
+hipError_t phase_end(atm3_ctx* ctx, int phase) { return phase_event(ctx, phase, 1); }
+
 bool make_grid(const double box[3], double rc, Grid* g) {
   int64_t total = 1;
   for (int d = 0; d < 3; ++d) {
@@ -113,6 +131,8 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if ((r = ensure(ctx, B_BLKD, 8 * 3 * C))) return r;
   if ((r = ensure(ctx, B_BLKI, 4 * 2 * C))) return r;
   if ((r = ensure(ctx, B_DEFER, 4 * (C + 2)))) return r;
+  if ((r = ensure(ctx, B_RED, reduce_scratch_bytes()))) return r;
+  if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
   return ATM3_OK;
 }
 
@@ -154,6 +174,8 @@ void atm3_destroy(atm3_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (int b = 0; b < B_NBUF; ++b)
     if (ctx->s.p[b]) (void)hipFree(ctx->s.p[b]);
+  for (int q = 0; q < NPHASE; ++q)
+    for (hipEvent_t e : ctx->timer[q].ev) (void)hipEventDestroy(e);
   if (ctx->dres) (void)hipFree(ctx->dres);
   if (ctx->hres) (void)hipHostFree(ctx->hres);
   delete ctx;
@@ -162,6 +184,37 @@ void atm3_destroy(atm3_ctx* ctx) {
 int atm3_set_stream(atm3_ctx* ctx, void* hip_stream) {
   if (!ctx) return ATM3_EINVAL;
   ctx->stream = (hipStream_t)hip_stream;
+  return ATM3_OK;
+}
+
+int atm3_profile_enable(atm3_ctx* ctx, int enable) {
+  if (!ctx) return ATM3_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  ctx->profile = enable != 0;
+  for (int q = 0; q < NPHASE; ++q) {
+    ctx->timer[q].used = 0;
+    ctx->timer[q].total_ms = 0.0;
+    ctx->timer[q].launches = 0;
+  }
+  return ATM3_OK;
+}
+
+int atm3_profile_read(atm3_ctx* ctx, int phase, double* total_ms, int64_t* launches) {
+  if (!ctx || phase < 0 || phase >= NPHASE || !total_ms || !launches) return ATM3_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  PhaseTimer& t = ctx->timer[phase];
+  for (size_t k = 0; k < t.used; ++k) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipEventElapsedTime");
+    t.total_ms += ms;
+    ++t.launches;
+  }
+  t.used = 0;
+  *total_ms = t.total_ms;
+  *launches = t.launches;
   return ATM3_OK;
 }
 
@@ -188,6 +241,7 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
   if ((r = ensure(ctx, B_START, 4 * (C + 1)))) return r;
   if ((r = ensure(ctx, B_PERM, 4 * N))) return r;
   if ((r = ensure(ctx, B_SORTED, 32 * N))) return r;
+  if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
   hipError_t e = launch_binning(ctx, pos, n, g);
   if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
   e = hipMemcpyAsync(cell_of, ctx->s.p[B_CELL_OF], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
@@ -220,8 +274,11 @@ int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const doubl
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "result copy");
   *out = *ctx->hres;
-  if (out->status != ATM3_OK)
+  if (out->status == ATM3_EOVERFLOW)
     return fail(ctx, out->status, "a 2x2x2 block of cells holds more than 512 molecules");
+  if (out->status == ATM3_ERANGE)
+    return fail(ctx, out->status, "a force contribution or sum reached 2^31 (fixed-point accumulator range)");
+  if (out->status != ATM3_OK) return fail(ctx, out->status, "evaluation failed");
   return ATM3_OK;
 }
 

@@ -52,31 +52,66 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
   rank[i] = atomicAdd(&count[c], 1);
 }
 
-// Exclusive prefix over the cell counts, one workgroup of 1024 threads:
-// each thread sums a contiguous chunk, the chunk sums are scanned in LDS.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count, int32_t* __restrict__ start,
-                                               int64_t ncells) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (ncells + 1023) / 1024;
-  const int64_t lo = (int64_t)t * per;
-  const int64_t hi = lo + per < ncells ? lo + per : ncells;
-  int32_t s = 0;
-  for (int64_t k = lo; k < hi; ++k) s += count[k];
-  part[t] = s;
+// Exclusive prefix over the cell counts in three steps: each workgroup scans
+// a tile of 1024 cells (4 consecutive cells per thread) and records the tile
+// sum; one workgroup scans the tile sums; the tile offsets are added.
+constexpr int TILE = 1024;
+
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(const int32_t* __restrict__ count, int32_t* __restrict__ start,
+                                                    int32_t* __restrict__ tile_sum, int64_t ncells) {
+  __shared__ int32_t ws[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * TILE + 4 * tid;
+  int v[4];
+  for (int k = 0; k < 4; ++k) v[k] = (c0 + k < ncells) ? count[c0 + k] : 0;
+  const int s = v[0] + v[1] + v[2] + v[3];
+  const int incl = wave_incl_scan(s, lane);
+  if (lane == 63) ws[wave] = incl;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = (t >= off) ? part[t - off] : 0;
+  int run = incl - s;
+  for (int q = 0; q < wave; ++q) run += ws[q];
+  for (int k = 0; k < 4; ++k) {
+    if (c0 + k < ncells) start[c0 + k] = run;
+    run += v[k];
+  }
+  if (tid == 255) tile_sum[blockIdx.x] = run;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t* __restrict__ tile_sum, int32_t ntiles) {
+  __shared__ int32_t ws[16];
+  __shared__ int32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < ntiles; base += 1024) {
+    const int t = base + tid;
+    const int v = (t < ntiles) ? tile_sum[t] : 0;
+    const int incl = wave_incl_scan(v, lane);
+    if (lane == 63) ws[wave] = incl;
     __syncthreads();
-    part[t] += v;
+    int pre = carry;
+    for (int q = 0; q < wave; ++q) pre += ws[q];
+    if (t < ntiles) tile_sum[t] = pre + incl - v;
+    __syncthreads();
+    if (tid == 1023) carry = pre + incl;
     __syncthreads();
   }
-  int32_t run = (t == 0) ? 0 : part[t - 1];
-  for (int64_t k = lo; k < hi; ++k) {
-    start[k] = run;
-    run += count[k];
-  }
-  if (t == 1023) start[ncells] = part[1023];
+  if (tid == 0) tile_sum[ntiles] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int32_t* __restrict__ start, const int32_t* __restrict__ tile_sum,
+                                                  int64_t ncells, int32_t ntiles) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c < ncells) start[c] += tile_sum[c / TILE];
+  if (c == 0) start[ncells] = tile_sum[ntiles];
 }
 
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
@@ -144,13 +179,22 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
   const int32_t nn = (int32_t)n;
   unsigned fb = blocks_for(gr.ncells, 256);
   if (fb > 4096) fb = 4096;
+  hipError_t e = phase_begin(ctx, ATM3_PHASE_BINNING);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, count, gr.ncells, 0);
   hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, nn, g, cell_of, rank, count);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, count, start, gr.ncells);
+  const int32_t ntiles = (int32_t)((gr.ncells + TILE - 1) / TILE);
+  int32_t* tile_sum = (int32_t*)ctx->s.p[B_TILE];
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, st, count, start, tile_sum, gr.ncells);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
+  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, tile_sum, gr.ncells,
+                     ntiles);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, cell_of, rank, start, nn, perm);
   hipLaunchKernelGGL(k_cellsort, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, gr.ncells, perm);
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, nn, g, sorted);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return phase_end(ctx, ATM3_PHASE_BINNING);
 }
 
 }  // namespace atm3

@@ -6,29 +6,35 @@
 // owned by the block whose base is the componentwise minimum of its cells,
 // i.e. iff the AND of the corner codes is 0; every pair/triplet whose cells
 // span at most one step per dimension is then counted exactly once over all
-// blocks (for a single base cell this is the one-cell set, 13 two-cell sets
-// and 44 three-cell sets; Sec. 3 eqs. celltriplet, twoonetriplets,
-// carttriplets).
+// blocks (for a single base cell: the one-cell set, 13 two-cell sets and 44
+// three-cell sets; Sec. 3 eqs. celltriplet, twoonetriplets, carttriplets).
 //
 // Per block:
 //  1. stage block-frame coordinates (cell-centred + corner shift) in FP64,
 //     and their single rounding to FP32;
-//  2. pair bit masks via wave ballots: bit j of row i set iff r_ij^2 < rc^2;
-//     FP32 test with a guard band, FP64 re-check with the exact
-//     minimum-image formula of the oracle inside the band;
-//  3. LJ over owned pairs (FP64 from the FP64 block frame); per row i the
-//     number of owned triplets
+//  2. upper-triangle pair bit masks by wave ballots: bit j of row i (j > i)
+//     set iff r_ij^2 < rc^2; FP32 test with a guard band, FP64 re-check with
+//     the oracle's exact minimum-image formula inside the band; the upper
+//     pairs are listed as they are found;
+//  3. per pair (contiguous chunk per thread): LJ if the block owns the pair
+//     (FP64), and the owned third molecules
 //     K(i,j) = mask_i & mask_j & allowed(code_i & code_j) & {k > j};
-//  4. prefix over rows, compact the triplets (i,j,k) into an LDS list;
-//  5. per triplet ATM math (FP32): eq. (atm) and its gradient in squared
-//     sides, the force pairs of eq. (forcepairs), LDS float atomics;
-//  6. per-corner partial forces to HBM in FP64 (each (corner, molecule)
-//     written by exactly one block, no global atomics), per-block
-//     energy/count partials.
-// Accumulation: the LJ part of each molecule's force is summed in FP64 (its
-// pair terms are large and cancel), the ATM part in FP32 LDS atomics.
-// A gather kernel sums the eight corner partials per molecule in fixed order
-// and a one-workgroup kernel reduces the per-block partials.
+//  4. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
+//     eq. forcepairs).  Each thread decodes an equal share of the block's
+//     triplets on the fly from the pair list and the sets K(i,j), so p_i,
+//     p_j and the accumulators of F_i, F_j stay in registers for a pair and
+//     only F_k is scattered per triplet;
+//  5. per-corner partial forces to HBM (each (corner, molecule) written by
+//     exactly one block, no global atomics); per-block energy and count
+//     partials.
+// Force accumulation is 64-bit fixed point (units of 2^-32): every FP64 (LJ)
+// or FP32 (ATM) contribution is converted exactly (truncated below 2^-32) and
+// added with LDS integer atomics, so the sums are exact and independent of
+// the order of arrival.  Blocks of more than 128 molecules take a general
+// path that materialises the triplets in rounds.  A gather kernel sums the
+// eight corner partials per molecule; two reduction kernels sum the
+// per-block partials in fixed order.  Every result is reproducible bit for
+// bit from run to run.
 #include "atm3_internal.h"
 
 namespace atm3 {
@@ -36,30 +42,36 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int NWAVE = WG / 64;
+constexpr int RBLK = 256;  // workgroups of the first reduction stage
+constexpr double FIX_SCALE = 4294967296.0;        // 2^32
+constexpr double FIX_INV = 2.3283064365386963e-10;  // 2^-32
+constexpr double FIX_LIMIT = 2147483648.0;        // |value| < 2^31
+
+typedef unsigned long long u64;
 
 struct ForceArgs {
-  const double4* sorted; // cell-centred FP64 coordinates, .w = input index
-  const int32_t* start;  // cell_start
-  const double* pos;     // FP64 input positions (exact re-checks only)
-  double* fpart;         // [8][3][N]
-  double* blkd;          // [C][3]
-  int32_t* blki;         // [C][2]
-  int32_t* defer;        // [0] count, [1] status, [2..] base cells
+  const double4* sorted;  // cell-centred FP64 coordinates, .w = input index
+  const int32_t* start;   // cell_start
+  const double* pos;      // FP64 input positions (exact re-checks only)
+  u64* fpart;             // [8][3][N] fixed point
+  double* blkd;           // [C][3]: e_lj', w_lj', e_atm'
+  int32_t* blki;          // [C][2]: pairs, triplets
+  int32_t* defer;         // [0] count, [1] status, [2..] base cells
   int32_t ntot;
   int32_t nx, ny, nz;
   int32_t ncells;
   int32_t terms;
-  double half[3]; // side_d / 2
-  float lo2, hi2; // FP32 guard band around rc^2
-  double rc2;     // rc^2 in FP64 (exact decision)
+  double half[3];  // side_d / 2
+  float lo2, hi2;  // FP32 guard band around rc^2
+  double rc2;      // rc^2 in FP64 (exact decision)
   double box[3];
-  double sig2;    // sigma^2
-  double eps24;   // 24 eps
+  double sig2;   // sigma^2
+  double eps24;  // 24 eps
   float k3nu, k15nu, k075nu;  // 3 nu, 1.875 nu, 0.75 nu
 };
 
 // Bits strictly above position i within 64-bit word w.
-__device__ __forceinline__ uint64_t above(int i, int w) {
+__device__ __forceinline__ u64 above(int i, int w) {
   int d = i - 64 * w;
   if (d < 0) return ~0ull;
   if (d >= 63) return 0ull;
@@ -83,313 +95,685 @@ __device__ __noinline__ double exact_r2(const double* __restrict__ pos, int a, i
   return s;
 }
 
+// d in units of 2^-32 as a two's-complement 64-bit integer, rounded toward
+// minus infinity: floor(d) in the high word, the fraction in the low word
+// (both exact in FP64).  Out-of-range or non-finite values set *bad.
+__device__ __forceinline__ u64 to_fix(double d, int* bad) {
+  if (!(fabs(d) < FIX_LIMIT)) {
+    *bad = 1;
+    return 0ull;
+  }
+  const double hi = floor(d);
+  const double lo = (d - hi) * FIX_SCALE;  // in [0, 2^32)
+  return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)(uint32_t)lo;
+}
+
+__device__ __forceinline__ double from_fix(u64 v) { return (double)(long long)v * FIX_INV; }
+
+__device__ __forceinline__ void add_fix(u64* ax, u64* ay, u64* az, int m, double x, double y, double z, int* bad) {
+  atomicAdd(&ax[m], to_fix(x, bad));
+  atomicAdd(&ay[m], to_fix(y, bad));
+  atomicAdd(&az[m], to_fix(z, bad));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
-__device__ __forceinline__ int wave_sum_i(int v) {
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   return v;
 }
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const int u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
 
-template <int NW, int TCAP>
-struct Lds {
-  static constexpr int MAXB = 64 * NW;
-  double dx[MAXB], dy[MAXB], dz[MAXB];
-  float sx[MAXB], sy[MAXB], sz[MAXB];
-  float fx[MAXB], fy[MAXB], fz[MAXB];    // ATM part
-  double gx[MAXB], gy[MAXB], gz[MAXB];   // LJ part
-  uint64_t mask[MAXB * NW];
-  uint64_t allow[8 * NW];
-  int32_t sorig[MAXB];
-  int32_t sslot[MAXB];
-  int32_t rowoff[MAXB + 1];
-  uint32_t tlist[TCAP];
-  uint8_t scode[MAXB];
-  int32_t cbase[9];
-  int32_t cstart[8];
-  double red[3][NWAVE];
-  int32_t redi[2][NWAVE];
+__device__ __forceinline__ int64_t comb2(int64_t n) { return n * (n - 1) / 2; }
+__device__ __forceinline__ int64_t comb3(int64_t n) { return n * (n - 1) * (n - 2) / 6; }
+
+// Molecule triplets of the cell sets a base cell visits (3c08), from the
+// populations N[o] of its eight corner cells: eq. (celltriplet) for the base
+// cell, eq. (twoonetriplets) for the 13 cell pairs and eq. (carttriplets) for
+// the 44 cell triples whose componentwise minimum is the base (corner codes
+// with AND == 0).
+__device__ int64_t candidates_3c08(const int32_t* N) {
+  int64_t t = comb3(N[0]);
+  for (int p = 0; p < 8; ++p)
+    for (int q = p + 1; q < 8; ++q) {
+      if ((p & q) == 0) t += (int64_t)N[q] * comb2(N[p]) + (int64_t)N[p] * comb2(N[q]);
+      for (int r = q + 1; r < 8; ++r)
+        if ((p & q & r) == 0) t += (int64_t)N[p] * N[q] * N[r];
+    }
+  return t;
+}
+
+// One ATM triplet in FP32 from block-frame positions: returns the energy
+// term without nu (Q^-3/2 + 3/8 P Q^-5/2) and the forces on i and j; the
+// force on k is -(F_i + F_j) (eq. newton3rdlaw).
+struct Trip {
+  float eu, fix, fiy, fiz, fjx, fjy, fjz;
 };
 
-// Process base cell b.  Returns false (uniformly) if the block is too large.
-template <int NW, int TCAP>
-__device__ bool do_block(const ForceArgs& a, int b, Lds<NW, TCAP>& L) {
-  constexpr int MAXB = 64 * NW;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
-  const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
+__device__ __forceinline__ Trip atm_triplet(const float4 pi, const float4 pj, const float4 pk, float k3nu,
+                                            float k15nu, float k075nu) {
+  const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
+  const float ikx = pi.x - pk.x, iky = pi.y - pk.y, ikz = pi.z - pk.z;
+  const float jkx = pj.x - pk.x, jky = pj.y - pk.y, jkz = pj.z - pk.z;
+  const float x = ijx * ijx + ijy * ijy + ijz * ijz;
+  const float y = ikx * ikx + iky * iky + ikz * ikz;
+  const float z = jkx * jkx + jky * jky + jkz * jkz;
+  // eq. (atm) in squared sides: u = nu [Q^-3/2 + 3/8 P Q^-5/2],
+  // Q = xyz, P = (y+z-x)(x+z-y)(x+y-z) = A B C.
+  const float s = x + y + z;
+  const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
+  const float AB = A * B, AC = A * C, BC = B * C;
+  const float P = AB * C;
+  const float S = AB + AC + BC;
+  const float xy = x * y, yz = y * z, xz = x * z;
+  const float Q = xy * z;
+  const float t1 = __builtin_amdgcn_rsqf(Q);
+  const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
+  Trip r;
+  r.eu = fmaf(0.375f * P, t5, t3);
+  // c_x = -2 du/dx = nu [3 t3 / x + 15/8 P t5 / x - 3/4 t5 dP/dx],
+  // dP/dx = S - 2BC (cyclic for y, z); 1/x = yz / Q.
+  const float G = fmaf(k15nu * P, t5, k3nu * t3);
+  const float H = k075nu * t5;
+  const float cx = fmaf(G, yz * t2, -H * fmaf(-2.f, BC, S));
+  const float cy = fmaf(G, xz * t2, -H * fmaf(-2.f, AC, S));
+  const float cz = fmaf(G, xy * t2, -H * fmaf(-2.f, AB, S));
+  // eq. (forcepairs): F_i = F_i(j)k + F_i(k)j, F_j = -F_i(j)k + F_j(k)i,
+  // with F_i(j)k = c_x r_ij, F_i(k)j = c_y r_ik, F_j(k)i = c_z r_jk.
+  r.fix = fmaf(cx, ijx, cy * ikx);
+  r.fiy = fmaf(cx, ijy, cy * iky);
+  r.fiz = fmaf(cx, ijz, cy * ikz);
+  r.fjx = fmaf(cz, jkx, -cx * ijx);
+  r.fjy = fmaf(cz, jky, -cx * ijy);
+  r.fjz = fmaf(cz, jkz, -cx * ijz);
+  return r;
+}
 
+// LJ pair term in FP64 on block-frame displacement e = r_i - r_j; returns
+// the force factor f (F_i = f e) and adds s12 - s6 and 2 s12 - s6 to the
+// energy and virial accumulators (scaled by 4 eps and 24 eps at the end).
+__device__ __forceinline__ double lj_pair(double ex, double ey, double ez, double sig2, double eps24, double* e_lj,
+                                          double* w_lj) {
+  // 4 eps [(s/r)^12 - (s/r)^6]; F_i = 24 eps [2 (s/r)^12 - (s/r)^6] r_ij / r^2
+  const double r2 = ex * ex + ey * ey + ez * ez;
+  const double ir2 = 1.0 / r2;
+  const double s2 = sig2 * ir2;
+  const double s6 = s2 * s2 * s2;
+  const double s12 = s6 * s6;
+  *e_lj += s12 - s6;
+  const double g = 2.0 * s12 - s6;
+  *w_lj += g;
+  return eps24 * g * ir2;
+}
+
+// Shared per-block bookkeeping of both paths.
+struct BlockHead {
+  int32_t cbase[9];
+  int32_t cstart[8];
+  int32_t wsum[NWAVE];
+  int32_t bad;
+  double red[3][NWAVE];
+  long long redi[NWAVE];
+};
+
+// Cell ranges of the eight corners of base cell b; returns the population.
+__device__ int block_cells(const ForceArgs& a, int b, BlockHead& H) {
+  const int tid = threadIdx.x;
   const int bx = b % a.nx, by = (b / a.nx) % a.ny, bz = b / (a.nx * a.ny);
   if (tid < 8) {
     int cx = bx + (tid & 1), cy = by + ((tid >> 1) & 1), cz = bz + (tid >> 2);
     if (cx >= a.nx) cx -= a.nx;
     if (cy >= a.ny) cy -= a.ny;
     if (cz >= a.nz) cz -= a.nz;
-    int c = (cz * a.ny + cy) * a.nx + cx;
-    int s0 = a.start[c];
-    L.cstart[tid] = s0;
-    L.cbase[tid + 1] = a.start[c + 1] - s0;  // count, prefixed below
+    const int c = (cz * a.ny + cy) * a.nx + cx;
+    const int s0 = a.start[c];
+    H.cstart[tid] = s0;
+    H.cbase[tid + 1] = a.start[c + 1] - s0;
   }
   __syncthreads();
   if (tid == 0) {
-    L.cbase[0] = 0;
-    for (int o = 0; o < 8; ++o) L.cbase[o + 1] += L.cbase[o];
+    H.cbase[0] = 0;
+    for (int o = 0; o < 8; ++o) H.cbase[o + 1] += H.cbase[o];
+    H.bad = 0;
   }
   __syncthreads();
-  const int n = L.cbase[8];
-  if (n > MAXB) return false;
+  return H.cbase[8];
+}
 
-  // 1. stage
-  for (int t = tid; t < n; t += WG) {
+// Stage block-frame coordinates, corner codes, input and sorted indices, and
+// clear the force accumulators.
+__device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, double4* dp, float4* sp, u64* ax,
+                            u64* ay, u64* az, uint8_t* scode, int32_t* sorig, int32_t* sslot) {
+  for (int t = threadIdx.x; t < n; t += WG) {
     int o = 0;
-    while (o < 7 && L.cbase[o + 1] <= t) ++o;
-    const int s = L.cstart[o] + (t - L.cbase[o]);
+    while (o < 7 && H.cbase[o + 1] <= t) ++o;
+    const int s = H.cstart[o] + (t - H.cbase[o]);
     const double4 v = a.sorted[s];
     const double px = v.x + ((o & 1) ? a.half[0] : -a.half[0]);
     const double py = v.y + ((o & 2) ? a.half[1] : -a.half[1]);
     const double pz = v.z + ((o & 4) ? a.half[2] : -a.half[2]);
-    L.dx[t] = px;
-    L.dy[t] = py;
-    L.dz[t] = pz;
-    L.sx[t] = (float)px;
-    L.sy[t] = (float)py;
-    L.sz[t] = (float)pz;
-    L.fx[t] = 0.f;
-    L.fy[t] = 0.f;
-    L.fz[t] = 0.f;
-    L.gx[t] = 0.0;
-    L.gy[t] = 0.0;
-    L.gz[t] = 0.0;
-    L.scode[t] = (uint8_t)o;
-    L.sorig[t] = (int32_t)v.w;
-    L.sslot[t] = s;
+    dp[t] = make_double4(px, py, pz, 0.0);
+    sp[t] = make_float4((float)px, (float)py, (float)pz, 0.f);
+    ax[t] = 0ull;
+    ay[t] = 0ull;
+    az[t] = 0ull;
+    scode[t] = (uint8_t)o;
+    sorig[t] = (int32_t)v.w;
+    sslot[t] = s;
   }
-  __syncthreads();
+}
 
-  // allowed-third masks: bit j of allow[c] iff (code_j & c) == 0
+// Allowed-third masks: bit j of allow[c] iff (code_j & c) == 0.
+template <int NW>
+__device__ void block_allow(int n, const uint8_t* scode, u64* allow) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int item = wave; item < 8 * NW; item += NWAVE) {
     const int c = item / NW, w = item % NW;
     const int j = 64 * w + lane;
-    const bool ok = (j < n) && ((L.scode[j] & c) == 0);
-    const uint64_t bits = __ballot(ok);
-    if (lane == 0) L.allow[item] = bits;
+    const bool ok = (j < n) && ((scode[j] & c) == 0);
+    const u64 bits = __ballot(ok);
+    if (lane == 0) allow[item] = bits;
   }
+}
 
-  // 2. pair masks
-  for (int item = wave; item < n * NW; item += NWAVE) {
-    const int i = item / NW, w = item % NW;
-    const int j = 64 * w + lane;
-    const bool valid = (j < n) && (j != i);
-    float r2 = 3.0e38f;
-    if (valid) {
-      const float dx = L.sx[i] - L.sx[j], dy = L.sy[i] - L.sy[j], dz = L.sz[i] - L.sz[j];
-      r2 = dx * dx + dy * dy + dz * dz;
-    }
-    const bool in = r2 < a.lo2;
-    const bool maybe = !in && r2 < a.hi2;
-    uint64_t bits = __ballot(in);
-    if (__ballot(maybe)) {
-      bool ex = false;
-      if (maybe) ex = exact_r2(a.pos, L.sorig[i], L.sorig[j], a.box[0], a.box[1], a.box[2]) < a.rc2;
-      bits |= __ballot(ex);
-    }
-    if (lane == 0) L.mask[i * NW + w] = bits;
+// Upper-triangle mask word (bits j > i of word w) of row i, one wave.
+__device__ __forceinline__ u64 mask_word(const ForceArgs& a, int i, int w, int n, const float4 pi, const float4 pj,
+                                         const int32_t* sorig) {
+  const int lane = threadIdx.x & 63;
+  const int j = 64 * w + lane;
+  const bool valid = (j > i) && (j < n);
+  const float ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
+  const float r2 = valid ? ex * ex + ey * ey + ez * ez : 3.0e38f;
+  const bool in = r2 < a.lo2;
+  const bool maybe = !in && r2 < a.hi2;
+  u64 bits = __ballot(in);
+  if (__ballot(maybe)) {
+    bool exq = false;
+    if (maybe) exq = exact_r2(a.pos, sorig[i], sorig[j], a.box[0], a.box[1], a.box[2]) < a.rc2;
+    bits |= __ballot(exq);
   }
-  __syncthreads();
+  return bits;
+}
 
-  // 3. LJ over owned pairs (FP64); triplet counts per row
-  double e_lj = 0.0, w_lj = 0.0;
-  int n_pair = 0;
-  for (int i = tid; i < n; i += WG) {
-    const int ci = L.scode[i];
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    int cnt = 0;
-    for (int w = i >> 6; w < NW; ++w) {
-      uint64_t mj = L.mask[i * NW + w] & above(i, w);
-      while (mj) {
-        const int j = 64 * w + __builtin_ctzll(mj);
-        mj &= mj - 1;
-        const int cij = ci & L.scode[j];
-        if (do_lj && cij == 0) {
-          // 4 eps [(s/r)^12 - (s/r)^6]; F_i = 24 eps [2 (s/r)^12 - (s/r)^6] r_ij / r^2
-          const double ex = L.dx[i] - L.dx[j], ey = L.dy[i] - L.dy[j], ez = L.dz[i] - L.dz[j];
-          const double r2 = ex * ex + ey * ey + ez * ez;
-          const double ir2 = 1.0 / r2;
-          const double s2 = a.sig2 * ir2;
-          const double s6 = s2 * s2 * s2;
-          const double s12 = s6 * s6;
-          e_lj += s12 - s6;
-          const double g = 2.0 * s12 - s6;
-          w_lj += g;
-          const double f = a.eps24 * g * ir2;
-          ax += f * ex;
-          ay += f * ey;
-          az += f * ez;
-          atomicAdd(&L.gx[j], -f * ex);
-          atomicAdd(&L.gy[j], -f * ey);
-          atomicAdd(&L.gz[j], -f * ez);
-          ++n_pair;
-        }
-        if (do_atm) {
-          const uint64_t* al = &L.allow[cij * NW];
-          for (int w2 = w; w2 < NW; ++w2)
-            cnt += __popcll(L.mask[i * NW + w2] & L.mask[j * NW + w2] & al[w2] & above(j, w2));
-        }
-      }
-    }
-    L.rowoff[i] = cnt;
-    if (do_lj) {
-      atomicAdd(&L.gx[i], ax);
-      atomicAdd(&L.gy[i], ay);
-      atomicAdd(&L.gz[i], az);
-    }
-  }
-  __syncthreads();
-
-  // 4./5. triplets
-  float e_atm = 0.f;
-  int total = 0;
-  if (do_atm) {
-    if (wave == 0) {  // exclusive scan of the row counts
-      int carry = 0;
-      for (int base = 0; base < n; base += 64) {
-        const int t = base + lane;
-        const int v = (t < n) ? L.rowoff[t] : 0;
-        int incl = v;
-        for (int off = 1; off < 64; off <<= 1) {
-          const int u = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += u;
-        }
-        if (t < n) L.rowoff[t] = carry + incl - v;
-        carry += __shfl(incl, 63, 64);
-      }
-      if (lane == 0) L.rowoff[n] = carry;
-    }
-    __syncthreads();
-    total = L.rowoff[n];
-    for (int rb = 0; rb < total; rb += TCAP) {
-      const int re = rb + TCAP;
-      for (int i = tid; i < n; i += WG) {
-        int p = L.rowoff[i];
-        if (L.rowoff[i + 1] <= rb || p >= re) continue;
-        const int ci = L.scode[i];
-        for (int w = i >> 6; w < NW; ++w) {
-          uint64_t mj = L.mask[i * NW + w] & above(i, w);
-          while (mj) {
-            const int j = 64 * w + __builtin_ctzll(mj);
-            mj &= mj - 1;
-            const uint64_t* al = &L.allow[(ci & L.scode[j]) * NW];
-            for (int w2 = w; w2 < NW; ++w2) {
-              uint64_t K = L.mask[i * NW + w2] & L.mask[j * NW + w2] & al[w2] & above(j, w2);
-              while (K) {
-                const int k = 64 * w2 + __builtin_ctzll(K);
-                K &= K - 1;
-                if (p >= rb && p < re) L.tlist[p - rb] = (uint32_t)i | ((uint32_t)j << 10) | ((uint32_t)k << 20);
-                ++p;
-              }
-            }
-          }
-        }
-      }
-      __syncthreads();
-      const int cnt = (total - rb < TCAP) ? total - rb : TCAP;
-      for (int t = tid; t < cnt; t += WG) {
-        const uint32_t e = L.tlist[t];
-        const int i = e & 1023, j = (e >> 10) & 1023, k = e >> 20;
-        const float xi = L.sx[i], yi = L.sy[i], zi = L.sz[i];
-        const float xj = L.sx[j], yj = L.sy[j], zj = L.sz[j];
-        const float xk = L.sx[k], yk = L.sy[k], zk = L.sz[k];
-        const float ijx = xi - xj, ijy = yi - yj, ijz = zi - zj;
-        const float ikx = xi - xk, iky = yi - yk, ikz = zi - zk;
-        const float jkx = xj - xk, jky = yj - yk, jkz = zj - zk;
-        const float x = ijx * ijx + ijy * ijy + ijz * ijz;
-        const float y = ikx * ikx + iky * iky + ikz * ikz;
-        const float z = jkx * jkx + jky * jky + jkz * jkz;
-        // eq. (atm) in squared sides: u = nu [Q^-3/2 + 3/8 P Q^-5/2],
-        // Q = xyz, P = (y+z-x)(x+z-y)(x+y-z) = A B C.
-        const float s = x + y + z;
-        const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
-        const float AB = A * B, AC = A * C, BC = B * C;
-        const float P = AB * C;
-        const float S = AB + AC + BC;
-        const float xy = x * y, yz = y * z, xz = x * z;
-        const float Q = xy * z;
-        const float t1 = __builtin_amdgcn_rsqf(Q);
-        const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
-        e_atm += fmaf(0.375f * P, t5, t3);
-        // c_x = -2 du/dx = nu [3 t3 / x + 15/8 P t5 / x - 3/4 t5 dP/dx],
-        // dP/dx = S - 2BC (cyclic for y, z); 1/x = yz / Q.
-        const float G = fmaf(a.k15nu * P, t5, a.k3nu * t3);
-        const float H = a.k075nu * t5;
-        const float cx = fmaf(G, yz * t2, -H * fmaf(-2.f, BC, S));
-        const float cy = fmaf(G, xz * t2, -H * fmaf(-2.f, AC, S));
-        const float cz = fmaf(G, xy * t2, -H * fmaf(-2.f, AB, S));
-        // eq. (forcepairs): F_i = F_i(j)k + F_i(k)j, F_j = -F_i(j)k + F_j(k)i,
-        // F_k = -F_i(k)j - F_j(k)i with F_i(j)k = c_x r_ij etc.
-        const float fix = fmaf(cx, ijx, cy * ikx), fiy = fmaf(cx, ijy, cy * iky), fiz = fmaf(cx, ijz, cy * ikz);
-        const float fjx = fmaf(cz, jkx, -cx * ijx), fjy = fmaf(cz, jky, -cx * ijy), fjz = fmaf(cz, jkz, -cx * ijz);
-        atomicAdd(&L.fx[i], fix);
-        atomicAdd(&L.fy[i], fiy);
-        atomicAdd(&L.fz[i], fiz);
-        atomicAdd(&L.fx[j], fjx);
-        atomicAdd(&L.fy[j], fjy);
-        atomicAdd(&L.fz[j], fjz);
-        atomicAdd(&L.fx[k], -(fix + fjx));
-        atomicAdd(&L.fy[k], -(fiy + fjy));
-        atomicAdd(&L.fz[k], -(fiz + fjz));
-      }
-      __syncthreads();
-    }
-  }
-  __syncthreads();
-
-  // 6. per-corner partial forces and block partials
+// Per-corner partials (fixed point) and block energy / count partials.
+__device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* scode, const int32_t* sslot,
+                            const u64* ax, const u64* ay, const u64* az, BlockHead& H, double e_lj, double w_lj,
+                            double e_atm, long long n_pair, int n_trip, int bad) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = a.ntot;
   for (int t = tid; t < n; t += WG) {
-    const int o = L.scode[t], s = L.sslot[t];
-    a.fpart[(int64_t)(o * 3 + 0) * N + s] = L.gx[t] + (double)L.fx[t];
-    a.fpart[(int64_t)(o * 3 + 1) * N + s] = L.gy[t] + (double)L.fy[t];
-    a.fpart[(int64_t)(o * 3 + 2) * N + s] = L.gz[t] + (double)L.fz[t];
+    const int o = scode[t], s = sslot[t];
+    a.fpart[(int64_t)(o * 3 + 0) * N + s] = ax[t];
+    a.fpart[(int64_t)(o * 3 + 1) * N + s] = ay[t];
+    a.fpart[(int64_t)(o * 3 + 2) * N + s] = az[t];
   }
-  const double r0 = wave_sum(e_lj), r1 = wave_sum(w_lj), r2 = wave_sum((double)e_atm);
-  const int i0 = wave_sum_i(n_pair);
+  const double r0 = wave_sum(e_lj), r1 = wave_sum(w_lj), r2 = wave_sum(e_atm);
+  const long long i0 = wave_sum_ll(n_pair);
+  const bool anybad = __ballot(bad != 0) != 0ull;
   if (lane == 0) {
-    L.red[0][wave] = r0;
-    L.red[1][wave] = r1;
-    L.red[2][wave] = r2;
-    L.redi[0][wave] = i0;
+    H.red[0][wave] = r0;
+    H.red[1][wave] = r1;
+    H.red[2][wave] = r2;
+    H.redi[wave] = i0;
+    if (anybad) H.bad = 1;
   }
   __syncthreads();
   if (tid == 0) {
     double s0 = 0, s1 = 0, s2 = 0;
-    int np = 0;
+    long long npr = 0;
     for (int q = 0; q < NWAVE; ++q) {
-      s0 += L.red[0][q];
-      s1 += L.red[1][q];
-      s2 += L.red[2][q];
-      np += L.redi[0][q];
+      s0 += H.red[0][q];
+      s1 += H.red[1][q];
+      s2 += H.red[2][q];
+      npr += H.redi[q];
     }
     a.blkd[3 * (int64_t)b + 0] = s0;
     a.blkd[3 * (int64_t)b + 1] = s1;
     a.blkd[3 * (int64_t)b + 2] = s2;
-    a.blki[2 * (int64_t)b + 0] = np;
-    a.blki[2 * (int64_t)b + 1] = total;
+    a.blki[2 * (int64_t)b + 0] = (int32_t)npr;
+    a.blki[2 * (int64_t)b + 1] = n_trip;
+    if (H.bad) atomicMin(&a.defer[1], ATM3_ERANGE);
   }
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Fast path: at most 128 molecules; the pair list is kept in four per-wave
+// segments of SEG entries (wave w lists the rows i = w mod 4 in order).
+// ---------------------------------------------------------------------------
+template <int SEG>
+struct LdsFast {
+  static constexpr int MAXB = 128;
+  static constexpr int NW = 2;
+  BlockHead h;
+  double4 dp[MAXB];
+  float4 sp[MAXB];
+  u64 ax[MAXB], ay[MAXB], az[MAXB];
+  u64 mask[MAXB * NW];  // bits j > i only
+  u64 allow[8 * NW];
+  int32_t sorig[MAXB];
+  int32_t sslot[MAXB];
+  int32_t toff[WG + 1];
+  int32_t segpre[NWAVE + 1];
+  uint16_t plist[NWAVE * SEG];  // i | j << 7
+  uint8_t scode[MAXB];
+};
+
+template <int SEG>
+__device__ __forceinline__ int pslot(int q, const int32_t* segpre) {
+  const int w = (q >= segpre[1]) + (q >= segpre[2]) + (q >= segpre[3]);
+  return w * SEG + (q - segpre[w]);
+}
+
+template <int SEG>
+__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
+  constexpr int MAXB = 128, NW = 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
+  const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
+
+  const int n = block_cells(a, b, L.h);
+  if (n > MAXB) return false;
+  block_stage(a, L.h, n, L.dp, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
+  __syncthreads();
+  block_allow<NW>(n, L.scode, L.allow);
+
+  // 2. upper-triangle masks and the per-wave pair segments
+  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 pj0 = (lane < n) ? L.sp[lane] : zero4;
+  const float4 pj1 = (64 + lane < n) ? L.sp[64 + lane] : zero4;
+  int segn = 0;
+  for (int i = wave; i < n; i += NWAVE) {
+    const float4 pi = L.sp[i];
+    const u64 b0 = mask_word(a, i, 0, n, pi, pj0, L.sorig);
+    const u64 b1 = mask_word(a, i, 1, n, pi, pj1, L.sorig);
+    const int c0 = __popcll(b0);
+    const int tot = c0 + __popcll(b1);
+    if (lane == 0) {
+      L.mask[i * NW + 0] = b0;
+      L.mask[i * NW + 1] = b1;
+    }
+    if (segn + tot <= SEG) {
+      uint16_t* seg = &L.plist[wave * SEG + segn];
+      if ((b0 >> lane) & 1ull) seg[__popcll(b0 & ((1ull << lane) - 1ull))] = (uint16_t)(i | (lane << 7));
+      if ((b1 >> lane) & 1ull) seg[c0 + __popcll(b1 & ((1ull << lane) - 1ull))] = (uint16_t)(i | ((64 + lane) << 7));
+    }
+    segn += tot;
+  }
+  if (lane == 0) L.toff[wave] = segn;
+  __syncthreads();
+  if (tid == 0) {
+    L.segpre[0] = 0;
+    for (int w = 0; w < NWAVE; ++w) L.segpre[w + 1] = L.segpre[w] + L.toff[w];
+  }
+  const bool overflow = L.toff[0] > SEG || L.toff[1] > SEG || L.toff[2] > SEG || L.toff[3] > SEG;
+  __syncthreads();
+  if (overflow) return false;
+  const int np = L.segpre[NWAVE];
+
+  // 3. per pair (contiguous chunk per thread): LJ for owned pairs and the
+  //    number of owned third molecules
+  const int mp = (np + WG - 1) / WG;
+  const int q0 = tid * mp < np ? tid * mp : np;
+  const int q1 = q0 + mp < np ? q0 + mp : np;
+  double e_lj = 0.0, w_lj = 0.0;
+  long long n_pair = 0;
+  int mycnt = 0, bad = 0;
+  {
+    int cur = -1;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const int e = L.plist[pslot<SEG>(q, L.segpre)];
+      const int i = e & 127, j = e >> 7;
+      const int cij = L.scode[i] & L.scode[j];
+      if (do_atm) {
+        const u64* al = &L.allow[cij * NW];
+        mycnt += __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
+                 __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
+      }
+      if (do_lj && cij == 0) {
+        if (i != cur) {
+          if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+          cur = i;
+          fx = fy = fz = 0.0;
+        }
+        const double4 di = L.dp[i], dj = L.dp[j];
+        const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
+        const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
+        fx += f * ex;
+        fy += f * ey;
+        fz += f * ez;
+        add_fix(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &bad);
+        ++n_pair;
+      }
+    }
+    if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+  }
+
+  // triplet offsets per thread chunk
+  const int incl = wave_incl_scan(mycnt, lane);
+  if (lane == 63) L.h.wsum[wave] = incl;
+  __syncthreads();
+  int ntr = 0, myoff = incl - mycnt;
+  for (int w = 0; w < NWAVE; ++w) {
+    const int v = L.h.wsum[w];
+    if (w < wave) myoff += v;
+    ntr += v;
+  }
+
+  double e_atm = 0.0;
+  if (do_atm && ntr > 0) {
+    // 4. thread t takes triplets [t*m, (t+1)*m) of the block's order (pair
+    //    order, k ascending), starting from the chunk that holds t*m
+    L.toff[tid] = myoff;
+    if (tid == 0) L.toff[WG] = ntr;
+    __syncthreads();
+    const int m = (ntr + WG - 1) / WG;
+    const int T0 = tid * m < ntr ? tid * m : ntr;
+    const int T1 = T0 + m < ntr ? T0 + m : ntr;
+    float eu = 0.f;
+    if (T0 < T1) {
+      int lo = 0, hi = WG;  // toff[lo] <= T0 < toff[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.toff[mid] <= T0) lo = mid;
+        else hi = mid;
+      }
+      int rem = T0 - L.toff[lo];
+      int q = lo * mp;
+      int i = 0, j = 0;
+      u64 K0 = 0, K1 = 0;
+      for (;;) {  // skip whole pairs
+        const int e = L.plist[pslot<SEG>(q, L.segpre)];
+        i = e & 127;
+        j = e >> 7;
+        const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
+        K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
+        K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
+        const int c = __popcll(K0) + __popcll(K1);
+        if (rem < c) break;
+        rem -= c;
+        ++q;
+      }
+      for (; rem > 0; --rem) {  // skip within the pair
+        if (K0) K0 &= K0 - 1;
+        else K1 &= K1 - 1;
+      }
+      float4 pi = L.sp[i], pj = L.sp[j];
+      int ci = i, cj = j;
+      float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f;
+      for (int t = T0; t < T1; ++t) {
+        int k;
+        if (K0) {
+          k = __builtin_ctzll(K0);
+          K0 &= K0 - 1;
+        } else {
+          k = 64 + __builtin_ctzll(K1);
+          K1 &= K1 - 1;
+        }
+        const float4 pk = L.sp[k];
+        const Trip r = atm_triplet(pi, pj, pk, a.k3nu, a.k15nu, a.k075nu);
+        eu += r.eu;
+        aix += r.fix;
+        aiy += r.fiy;
+        aiz += r.fiz;
+        ajx += r.fjx;
+        ajy += r.fjy;
+        ajz += r.fjz;
+        add_fix(L.ax, L.ay, L.az, k, -(double)(r.fix + r.fjx), -(double)(r.fiy + r.fjy), -(double)(r.fiz + r.fjz),
+                &bad);
+        if ((K0 | K1) == 0 && t + 1 < T1) {
+          do {  // next pair with a non-empty K
+            ++q;
+            const int e = L.plist[pslot<SEG>(q, L.segpre)];
+            i = e & 127;
+            j = e >> 7;
+            const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
+            K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
+            K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
+          } while ((K0 | K1) == 0);
+          if (i != ci) {
+            add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+            aix = aiy = aiz = 0.f;
+            ci = i;
+            pi = L.sp[i];
+          }
+          if (j != cj) {
+            add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+            ajx = ajy = ajz = 0.f;
+            cj = j;
+            pj = L.sp[j];
+          }
+        }
+      }
+      add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+      add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+    }
+    e_atm = (double)eu;
+  }
+  __syncthreads();
+  block_flush(a, b, n, L.scode, L.sslot, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, bad);
   return true;
 }
 
-// Regular blocks (<= 64*NW molecules); larger ones are queued for k_block_big.
-// Workgroup ids are spread over the 8 XCDs round-robin; consecutive ids on one
-// XCD map to consecutive base cells so neighbouring blocks share its L2.
-template <int NW, int TCAP>
+// ---------------------------------------------------------------------------
+// General path for blocks of up to 64*NW molecules with any number of pairs
+// and triplets: pairs are compacted by ballot + prefix offsets in rounds of
+// PCAP, triplets materialised in rounds of TCAP.
+// ---------------------------------------------------------------------------
+template <int NW, int PCAP, int TCAP>
+struct LdsBig {
+  static constexpr int MAXB = 64 * NW;
+  BlockHead h;
+  double4 dp[MAXB];
+  float4 sp[MAXB];
+  u64 ax[MAXB], ay[MAXB], az[MAXB];
+  u64 mask[MAXB * NW];
+  u64 allow[8 * NW];
+  int32_t sorig[MAXB];
+  int32_t sslot[MAXB];
+  int32_t pw[MAXB * NW];  // upper-pair count per row word -> offsets
+  uint32_t plist[PCAP];   // i | j << 10
+  int32_t pcnt[PCAP];     // triplets per pair -> offsets
+  uint32_t tlist[TCAP];   // i | j << 10 | k << 20
+  uint8_t scode[MAXB];
+};
+
+// Exclusive prefix sum of data[0..M) in place, all threads of the block;
+// returns the total.  Each thread scans a contiguous chunk.
+__device__ int block_scan(int32_t* data, int M, int32_t* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int per = (M + WG - 1) / WG;
+  const int lo = tid * per < M ? tid * per : M;
+  const int hi = lo + per < M ? lo + per : M;
+  int s = 0;
+  for (int q = lo; q < hi; ++q) s += data[q];
+  const int incl = wave_incl_scan(s, lane);
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int wpre = 0, total = 0;
+  for (int q = 0; q < NWAVE; ++q) {
+    const int v = wsum[q];
+    if (q < wave) wpre += v;
+    total += v;
+  }
+  int run = wpre + incl - s;
+  for (int q = lo; q < hi; ++q) {
+    const int v = data[q];
+    data[q] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
+}
+
+template <int NW, int PCAP, int TCAP>
+__device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& L) {
+  constexpr int MAXB = 64 * NW;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
+  const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
+
+  const int n = block_cells(a, b, L.h);
+  if (n > MAXB) return false;
+  block_stage(a, L.h, n, L.dp, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
+  __syncthreads();
+  block_allow<NW>(n, L.scode, L.allow);
+
+  // upper-triangle masks
+  for (int i = wave; i < n; i += NWAVE) {
+    const float4 pi = L.sp[i];
+    for (int w = i >> 6; w < NW; ++w) {
+      const int j = 64 * w + lane;
+      const float4 pj = (j < n) ? L.sp[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const u64 bits = mask_word(a, i, w, n, pi, pj, L.sorig);
+      if (lane == 0) L.mask[i * NW + w] = bits;
+    }
+    if (lane == 0)
+      for (int w = 0; w < (i >> 6); ++w) L.mask[i * NW + w] = 0ull;
+  }
+  __syncthreads();
+  for (int q = tid; q < n * NW; q += WG) L.pw[q] = __popcll(L.mask[q]);
+  __syncthreads();
+  const int npairs = block_scan(L.pw, n * NW, L.h.wsum);
+
+  double e_lj = 0.0, w_lj = 0.0, e_atm = 0.0;
+  long long n_pair = 0;
+  int n_trip = 0, bad = 0;
+  for (int pr = 0; pr < npairs; pr += PCAP) {
+    const int np = (npairs - pr < PCAP) ? npairs - pr : PCAP;
+    for (int item = wave; item < n * NW; item += NWAVE) {
+      const int i = item / NW, w = item % NW;
+      const u64 bits = L.mask[item];
+      const int base = L.pw[item];
+      if (base >= pr + np || base + __popcll(bits) <= pr) continue;
+      if ((bits >> lane) & 1ull) {
+        const int p = base + __popcll(bits & ((1ull << lane) - 1ull));
+        if (p >= pr && p < pr + np) L.plist[p - pr] = (uint32_t)i | ((uint32_t)(64 * w + lane) << 10);
+      }
+    }
+    __syncthreads();
+
+    const int mp = ((np + WG - 1) / WG) | 1;
+    const int q0 = tid * mp < np ? tid * mp : np;
+    const int q1 = q0 + mp < np ? q0 + mp : np;
+    {
+      int cur = -1;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      for (int q = q0; q < q1; ++q) {
+        const uint32_t e = L.plist[q];
+        const int i = e & 1023, j = e >> 10;
+        const int cij = L.scode[i] & L.scode[j];
+        if (do_atm) {
+          const u64* al = &L.allow[cij * NW];
+          int c = 0;
+          for (int w2 = j >> 6; w2 < NW; ++w2)
+            c += __popcll(L.mask[i * NW + w2] & L.mask[j * NW + w2] & al[w2] & above(j, w2));
+          L.pcnt[q] = c;
+        }
+        if (do_lj && cij == 0) {
+          if (i != cur) {
+            if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+            cur = i;
+            fx = fy = fz = 0.0;
+          }
+          const double4 di = L.dp[i], dj = L.dp[j];
+          const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
+          const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
+          fx += f * ex;
+          fy += f * ey;
+          fz += f * ez;
+          add_fix(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &bad);
+          ++n_pair;
+        }
+      }
+      if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+    }
+    __syncthreads();
+    if (!do_atm) continue;
+
+    const int ntr = block_scan(L.pcnt, np, L.h.wsum);
+    n_trip += ntr;
+    for (int tr = 0; tr < ntr; tr += TCAP) {
+      const int nt = (ntr - tr < TCAP) ? ntr - tr : TCAP;
+      for (int q = q0; q < q1; ++q) {
+        int off = L.pcnt[q];
+        const int end = (q + 1 < np) ? L.pcnt[q + 1] : ntr;
+        if (end <= tr || off >= tr + nt) continue;
+        const uint32_t e = L.plist[q];
+        const int i = e & 1023, j = e >> 10;
+        const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
+        for (int w2 = j >> 6; w2 < NW; ++w2) {
+          u64 K = L.mask[i * NW + w2] & L.mask[j * NW + w2] & al[w2] & above(j, w2);
+          while (K) {
+            const int k = 64 * w2 + __builtin_ctzll(K);
+            K &= K - 1;
+            if (off >= tr && off < tr + nt) L.tlist[off - tr] = e | ((uint32_t)k << 20);
+            ++off;
+          }
+        }
+      }
+      __syncthreads();
+      const int m = ((nt + WG - 1) / WG) | 1;
+      const int t0 = tid * m < nt ? tid * m : nt;
+      const int t1 = t0 + m < nt ? t0 + m : nt;
+      int ci = -1, cj = -1;
+      float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f;
+      float eu = 0.f;
+      for (int t = t0; t < t1; ++t) {
+        const uint32_t e = L.tlist[t];
+        const int i = e & 1023, j = (e >> 10) & 1023, k = e >> 20;
+        if (i != ci) {
+          if (ci >= 0) add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+          ci = i;
+          aix = aiy = aiz = 0.f;
+        }
+        if (j != cj) {
+          if (cj >= 0) add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+          cj = j;
+          ajx = ajy = ajz = 0.f;
+        }
+        const Trip r = atm_triplet(L.sp[i], L.sp[j], L.sp[k], a.k3nu, a.k15nu, a.k075nu);
+        eu += r.eu;
+        aix += r.fix;
+        aiy += r.fiy;
+        aiz += r.fiz;
+        ajx += r.fjx;
+        ajy += r.fjy;
+        ajz += r.fjz;
+        add_fix(L.ax, L.ay, L.az, k, -(double)(r.fix + r.fjx), -(double)(r.fiy + r.fjy), -(double)(r.fiz + r.fjz),
+                &bad);
+      }
+      if (ci >= 0) add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+      if (cj >= 0) add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+      e_atm += (double)eu;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  block_flush(a, b, n, L.scode, L.sslot, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, n_trip, bad);
+  return true;
+}
+
+// Regular blocks; blocks with more than 128 molecules or more upper pairs
+// than a pair segment holds are queued for k_block_big.  Workgroup ids are
+// spread over the 8 XCDs round-robin; consecutive ids on one XCD map to
+// consecutive base cells so neighbouring blocks share its L2.
+template <int SEG>
 __global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
-  __shared__ Lds<NW, TCAP> L;
+  __shared__ LdsFast<SEG> L;
   const int per = (a.ncells + 7) / 8;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if ((blockIdx.x >> 3) >= per || b >= a.ncells) return;
-  if (!do_block<NW, TCAP>(a, b, L)) {
+  if (!do_block_fast<SEG>(a, b, L)) {
     if (threadIdx.x == 0) {
       const int q = atomicAdd(&a.defer[0], 1);
       a.defer[2 + q] = b;
@@ -397,18 +781,16 @@ __global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
   }
 }
 
-template <int NW, int TCAP>
+template <int NW, int PCAP, int TCAP>
 __global__ __launch_bounds__(WG) void k_block_big(ForceArgs a) {
-  __shared__ Lds<NW, TCAP> L;
+  __shared__ LdsBig<NW, PCAP, TCAP> L;
   const int nq = a.defer[0];
   for (int q = blockIdx.x; q < nq; q += gridDim.x) {
     const int b = a.defer[2 + q];
-    if (!do_block<NW, TCAP>(a, b, L)) {
+    if (!do_block_big<NW, PCAP, TCAP>(a, b, L)) {
       if (threadIdx.x == 0) {
-        a.defer[1] = ATM3_EOVERFLOW;
-        a.blkd[3 * (int64_t)b + 0] = 0.0;
-        a.blkd[3 * (int64_t)b + 1] = 0.0;
-        a.blkd[3 * (int64_t)b + 2] = 0.0;
+        atomicMin(&a.defer[1], ATM3_EOVERFLOW);
+        for (int k = 0; k < 3; ++k) a.blkd[3 * (int64_t)b + k] = 0.0;
         a.blki[2 * (int64_t)b + 0] = 0;
         a.blki[2 * (int64_t)b + 1] = 0;
       }
@@ -424,45 +806,43 @@ __global__ void k_reset(int32_t* defer) {
   }
 }
 
-// Sum the eight corner partials of each molecule in fixed order and write the
-// force in input order.
-__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ fpart, const int32_t* __restrict__ perm,
+// Sum the eight corner partials of each molecule (exact, fixed point) and
+// write the force in input order.
+__global__ __launch_bounds__(256) void k_finalize(const u64* __restrict__ fpart, const int32_t* __restrict__ perm,
                                                   int32_t N, float* __restrict__ forces) {
   const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= N) return;
-  double f[3];
+  float f[3];
   for (int d = 0; d < 3; ++d) {
-    double acc = 0.0;
+    u64 acc = 0ull;
     for (int o = 0; o < 8; ++o) acc += fpart[(int64_t)(o * 3 + d) * N + s];
-    f[d] = acc;
+    f[d] = (float)from_fix(acc);
   }
   const int64_t i = perm[s];
-  forces[3 * i + 0] = (float)f[0];
-  forces[3 * i + 1] = (float)f[1];
-  forces[3 * i + 2] = (float)f[2];
+  forces[3 * i + 0] = f[0];
+  forces[3 * i + 1] = f[1];
+  forces[3 * i + 2] = f[2];
 }
 
-__device__ __forceinline__ int64_t comb2(int64_t n) { return n * (n - 1) / 2; }
-__device__ __forceinline__ int64_t comb3(int64_t n) { return n * (n - 1) * (n - 2) / 6; }
+// Partial sums of one reduction workgroup: 4 doubles, 2 counts.
+struct RedPart {
+  double d[4];
+  long long c[2];
+};
 
-struct ReduceArgs {
+// Stage 1: workgroup g sums the blocks of its contiguous chunk, and the
+// traversal's candidate count of each of those base cells.
+struct Red1Args {
   const double* blkd;
   const int32_t* blki;
   const int32_t* start;
-  const int32_t* defer;
   int32_t nx, ny, nz, ncells;
-  int32_t variant;
-  double eps4, eps24, nu;
-  atm3_result* out;
+  RedPart* part;
 };
 
-// Molecule triplets of the cell sets base cell b visits (3c08): Sec. 3,
-// eq. (celltriplet) for the base cell, eq. (twoonetriplets) for the 13 cell
-// pairs and eq. (carttriplets) for the 44 cell triples of the 2x2x2 block
-// whose componentwise minimum is b (corner codes with AND == 0).
-__device__ int64_t candidates_3c08(const ReduceArgs& a, int b) {
+__device__ int64_t candidates_of(const Red1Args& a, int b) {
   const int bx = b % a.nx, by = (b / a.nx) % a.ny, bz = b / (a.nx * a.ny);
-  int64_t N[8];
+  int32_t N[8];
   for (int o = 0; o < 8; ++o) {
     int cx = bx + (o & 1), cy = by + ((o >> 1) & 1), cz = bz + (o >> 2);
     if (cx >= a.nx) cx -= a.nx;
@@ -471,66 +851,79 @@ __device__ int64_t candidates_3c08(const ReduceArgs& a, int b) {
     const int c = (cz * a.ny + cy) * a.nx + cx;
     N[o] = a.start[c + 1] - a.start[c];
   }
-  int64_t t = comb3(N[0]);
-  for (int p = 0; p < 8; ++p)
-    for (int q = p + 1; q < 8; ++q) {
-      if ((p & q) == 0) t += N[q] * comb2(N[p]) + N[p] * comb2(N[q]);
-      for (int r = q + 1; r < 8; ++r)
-        if ((p & q & r) == 0) t += N[p] * N[q] * N[r];
-    }
-  return t;
+  return candidates_3c08(N);
 }
 
-__global__ __launch_bounds__(1024) void k_reduce(ReduceArgs a) {
-  __shared__ double sd[3][1024 / 64];
-  __shared__ long long si[3][1024 / 64];
+__global__ __launch_bounds__(256) void k_reduce1(Red1Args ra) {
+  __shared__ double sd[4][4];
+  __shared__ long long sc[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double d0 = 0, d1 = 0, d2 = 0;
-  long long c0 = 0, c1 = 0, c2 = 0;
-  for (int b = tid; b < a.ncells; b += 1024) {
-    d0 += a.blkd[3 * (int64_t)b + 0];
-    d1 += a.blkd[3 * (int64_t)b + 1];
-    d2 += a.blkd[3 * (int64_t)b + 2];
-    c0 += a.blki[2 * (int64_t)b + 0];
-    c1 += a.blki[2 * (int64_t)b + 1];
-    c2 += candidates_3c08(a, b);
+  const int chunk = (ra.ncells + RBLK - 1) / RBLK;
+  const int lo = blockIdx.x * chunk;
+  const int hi = lo + chunk < ra.ncells ? lo + chunk : ra.ncells;
+  double d[4] = {0, 0, 0, 0};
+  long long c[2] = {0, 0};
+  for (int b = lo + tid; b < hi; b += 256) {
+    for (int k = 0; k < 3; ++k) d[k] += ra.blkd[3 * (int64_t)b + k];
+    d[3] += (double)candidates_of(ra, b);
+    c[0] += ra.blki[2 * (int64_t)b + 0];
+    c[1] += ra.blki[2 * (int64_t)b + 1];
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    d0 += __shfl_down(d0, off, 64);
-    d1 += __shfl_down(d1, off, 64);
-    d2 += __shfl_down(d2, off, 64);
-    c0 += __shfl_down(c0, off, 64);
-    c1 += __shfl_down(c1, off, 64);
-    c2 += __shfl_down(c2, off, 64);
-  }
+  for (int k = 0; k < 4; ++k) d[k] = wave_sum(d[k]);
+  c[0] = wave_sum_ll(c[0]);
+  c[1] = wave_sum_ll(c[1]);
   if (lane == 0) {
-    sd[0][wave] = d0;
-    sd[1][wave] = d1;
-    sd[2][wave] = d2;
-    si[0][wave] = c0;
-    si[1][wave] = c1;
-    si[2][wave] = c2;
+    for (int k = 0; k < 4; ++k) sd[k][wave] = d[k];
+    sc[0][wave] = c[0];
+    sc[1][wave] = c[1];
   }
   __syncthreads();
   if (tid == 0) {
-    double e0 = 0, e1 = 0, e2 = 0;
-    long long k0 = 0, k1 = 0, k2 = 0;
-    for (int q = 0; q < 1024 / 64; ++q) {
-      e0 += sd[0][q];
-      e1 += sd[1][q];
-      e2 += sd[2][q];
-      k0 += si[0][q];
-      k1 += si[1][q];
-      k2 += si[2][q];
+    RedPart r;
+    for (int k = 0; k < 4; ++k) r.d[k] = sd[k][0] + sd[k][1] + sd[k][2] + sd[k][3];
+    for (int k = 0; k < 2; ++k) r.c[k] = sc[k][0] + sc[k][1] + sc[k][2] + sc[k][3];
+    ra.part[blockIdx.x] = r;
+  }
+}
+
+struct ReduceArgs {
+  const RedPart* part;
+  const int32_t* defer;
+  int32_t nx, ny, nz;
+  double eps4, eps24, nu;
+  atm3_result* out;
+};
+
+// Stage 2: one workgroup sums the RBLK partials in fixed order.
+__global__ __launch_bounds__(RBLK) void k_reduce2(ReduceArgs a) {
+  __shared__ double sd[4][RBLK / 64];
+  __shared__ long long sc[2][RBLK / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const RedPart p = a.part[tid];
+  double d[4];
+  long long c[2];
+  for (int k = 0; k < 4; ++k) d[k] = wave_sum(p.d[k]);
+  for (int k = 0; k < 2; ++k) c[k] = wave_sum_ll(p.c[k]);
+  if (lane == 0) {
+    for (int k = 0; k < 4; ++k) sd[k][wave] = d[k];
+    for (int k = 0; k < 2; ++k) sc[k][wave] = c[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double e[4] = {0, 0, 0, 0};
+    long long q[2] = {0, 0};
+    for (int w = 0; w < RBLK / 64; ++w) {
+      for (int k = 0; k < 4; ++k) e[k] += sd[k][w];
+      for (int k = 0; k < 2; ++k) q[k] += sc[k][w];
     }
     atm3_result r;
-    r.e_lj = a.eps4 * e0;
-    r.w_lj = a.eps24 * e1;
-    r.e_atm = a.nu * e2;
-    r.w_atm = 9.0 * a.nu * e2;  // degree -9 homogeneity of eq. (atm): W_3 = 9 E_3
-    r.n_pairs = k0;
-    r.n_triplets = k1;
-    r.n_candidates = k2;
+    r.e_lj = a.eps4 * e[0];
+    r.w_lj = a.eps24 * e[1];
+    r.e_atm = a.nu * e[2];
+    r.w_atm = 9.0 * a.nu * e[2];  // degree -9 homogeneity of eq. (atm): W_3 = 9 E_3
+    r.n_pairs = q[0];
+    r.n_triplets = q[1];
+    r.n_candidates = (int64_t)e[3];
     r.ncell[0] = a.nx;
     r.ncell[1] = a.ny;
     r.ncell[2] = a.nz;
@@ -543,6 +936,8 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
+size_t reduce_scratch_bytes() { return sizeof(RedPart) * RBLK; }
+
 hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
                          float* forces, atm3_result* res_dev) {
   hipStream_t st = ctx->stream;
@@ -550,7 +945,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   a.sorted = (const double4*)ctx->s.p[B_SORTED];
   a.start = (const int32_t*)ctx->s.p[B_START];
   a.pos = pos;
-  a.fpart = (double*)ctx->s.p[B_FPART];
+  a.fpart = (u64*)ctx->s.p[B_FPART];
   a.blkd = (double*)ctx->s.p[B_BLKD];
   a.blki = (int32_t*)ctx->s.p[B_BLKI];
   a.defer = (int32_t*)ctx->s.p[B_DEFER];
@@ -565,7 +960,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
     a.box[d] = g.box[d];
   }
   const double rc2 = p.rc * p.rc;
-  // guard band: FP32 block-frame r^2 is within ~2e-6 relative of the exact
+  // guard band: FP32 block-frame r^2 is within ~1e-6 relative of the exact
   // value; a band of 4e-5 relative routes every uncertain pair to FP64
   a.lo2 = (float)(rc2 * (1.0 - 4e-5));
   a.hi2 = (float)(rc2 * (1.0 + 4e-5));
@@ -578,26 +973,40 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.defer);
   const int per = (a.ncells + 7) / 8;
-  hipLaunchKernelGGL((k_block<2, 4096>), dim3(8 * per), dim3(WG), 0, st, a);
-  hipLaunchKernelGGL((k_block_big<8, 2048>), dim3(256), dim3(WG), 0, st, a);
-  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const double*)a.fpart,
+  hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_block<1024>), dim3(8 * per), dim3(WG), 0, st, a);
+  if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
+  if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
+  if ((e = phase_end(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
+  if ((e = phase_begin(ctx, ATM3_PHASE_REDUCE)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const u64*)a.fpart,
                      (const int32_t*)ctx->s.p[B_PERM], (int32_t)n, forces);
+  RedPart* part = (RedPart*)ctx->s.p[B_RED];
+  Red1Args r1;
+  r1.blkd = a.blkd;
+  r1.blki = a.blki;
+  r1.start = a.start;
+  r1.nx = a.nx;
+  r1.ny = a.ny;
+  r1.nz = a.nz;
+  r1.ncells = a.ncells;
+  r1.part = part;
+  hipLaunchKernelGGL(k_reduce1, dim3(RBLK), dim3(256), 0, st, r1);
   ReduceArgs r;
-  r.blkd = a.blkd;
-  r.blki = a.blki;
-  r.start = a.start;
+  r.part = part;
   r.defer = a.defer;
   r.nx = a.nx;
   r.ny = a.ny;
   r.nz = a.nz;
-  r.ncells = a.ncells;
-  r.variant = p.variant;
   r.eps4 = 4.0 * p.eps;
   r.eps24 = 24.0 * p.eps;
   r.nu = p.nu;
   r.out = res_dev;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, st, r);
-  return hipGetLastError();
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(RBLK), 0, st, r);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return phase_end(ctx, ATM3_PHASE_REDUCE);
 }
 
 }  // namespace atm3

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "atm3.h"
 
@@ -30,7 +31,9 @@ enum Buf {
   B_FPART,        // double[8][3][N] per-corner partial forces (sorted order)
   B_BLKD,         // double[C][3] per-block e_lj', w_lj', e_atm'
   B_BLKI,         // int32 [C][2] per-block pair and triplet counts
-  B_DEFER,        // int32 [C+1] deferred (large) blocks; [0] = count
+  B_DEFER,        // int32 [C+2] [0] deferred count, [1] status, [2..] base cells
+  B_RED,          // first-stage reduction partials
+  B_TILE,         // int32 per-tile sums of the cell-count scan
   B_NBUF
 };
 
@@ -41,8 +44,21 @@ struct Scratch {
 
 }  // namespace atm3
 
+namespace atm3 {
+constexpr int NPHASE = 4;
+// HIP event pairs recorded around each timed phase (reused between reads).
+struct PhaseTimer {
+  std::vector<hipEvent_t> ev;  // start/stop interleaved
+  size_t used = 0;             // event pairs recorded since the last read
+  double total_ms = 0.0;
+  int64_t launches = 0;
+};
+}  // namespace atm3
+
 struct atm3_ctx {
   int device = 0;
+  bool profile = false;
+  atm3::PhaseTimer timer[atm3::NPHASE];
   hipStream_t stream = nullptr;
   std::string err;
   atm3::Scratch s;
@@ -51,6 +67,10 @@ struct atm3_ctx {
 };
 
 namespace atm3 {
+
+// Record the start / stop event of a timed phase (no-ops unless profiling).
+hipError_t phase_begin(atm3_ctx* ctx, int phase);
+hipError_t phase_end(atm3_ctx* ctx, int phase);
 
 // Status helpers (set ctx->err and return the code).
 int fail(atm3_ctx* ctx, int code, const std::string& msg);
@@ -66,6 +86,7 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
 
 // Forces (atm3_forces.hip): block kernels, per-corner partial forces, final
 // gather into `forces` and the reduction into `res_dev`.
+size_t reduce_scratch_bytes();
 hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g,
                          const atm3_params& p, float* forces, atm3_result* res_dev);
 
