@@ -19,12 +19,14 @@
 //  3. per pair (contiguous chunk per thread): LJ if the block owns the pair
 //     (FP64), and the owned third molecules
 //     K(i,j) = mask_i & mask_j & allowed(code_i & code_j) & {k > j};
-//  4. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
-//     eq. forcepairs).  Each thread decodes an equal share of the block's
-//     triplets on the fly from the pair list and the sets K(i,j), so p_i,
-//     p_j and the accumulators of F_i, F_j stay in registers for a pair and
-//     only F_k is scattered per triplet;
-//  5. per-corner partial forces to HBM (each (corner, molecule) written by
+//  4. the pairs with a non-empty K are compacted with their K words and
+//     the number of their first triplet;
+//  5. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
+//     eq. forcepairs).  Each thread takes an equal share of the block's
+//     triplets in (pair, k) order and decodes them from the compacted
+//     pairs, so p_i, p_j and the accumulators of F_i, F_j stay in registers
+//     for a pair and only F_k is scattered per triplet;
+//  6. per-corner partial forces to HBM (each (corner, molecule) written by
 //     exactly one block, no global atomics); per-block energy and count
 //     partials.
 // Force accumulation is 64-bit fixed point (units of 2^-32): every FP64 (LJ)
@@ -106,6 +108,24 @@ __device__ __forceinline__ u64 to_fix(double d, int* bad) {
   const double hi = floor(d);
   const double lo = (d - hi) * FIX_SCALE;  // in [0, 2^32)
   return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)(uint32_t)lo;
+}
+
+// FP32 variant, branch-free: magnitude split exactly into integer and
+// fraction (both exact in FP32), then the two's-complement negation.
+__device__ __forceinline__ u64 to_fix_f(float x, int* bad) {
+  const float a = fabsf(x);
+  *bad |= !(a < 2147483648.f);
+  const float fl = floorf(a);
+  const uint32_t hi = (uint32_t)fl;
+  const uint32_t lo = (uint32_t)((a - fl) * 4294967296.f);
+  const u64 v = ((u64)hi << 32) | (u64)lo;
+  return (x < 0.f) ? (u64)0 - v : v;
+}
+
+__device__ __forceinline__ void add_fix_f(u64* ax, u64* ay, u64* az, int m, float x, float y, float z, int* bad) {
+  atomicAdd(&ax[m], to_fix_f(x, bad));
+  atomicAdd(&ay[m], to_fix_f(y, bad));
+  atomicAdd(&az[m], to_fix_f(z, bad));
 }
 
 __device__ __forceinline__ double from_fix(u64 v) { return (double)(long long)v * FIX_INV; }
@@ -346,10 +366,12 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
 }
 
 // ---------------------------------------------------------------------------
-// Fast path: at most 128 molecules; the pair list is kept in four per-wave
-// segments of SEG entries (wave w lists the rows i = w mod 4 in order).
+// Fast path: at most 128 molecules; the upper pairs are listed in four
+// per-wave segments of SEG entries (wave w lists the rows i = w mod 4 in
+// order); the pairs with a non-empty K (about a third of them) are then
+// compacted with their K words and triplet offsets, at most KCAP of them.
 // ---------------------------------------------------------------------------
-template <int SEG>
+template <int SEG, int KCAP>
 struct LdsFast {
   static constexpr int MAXB = 128;
   static constexpr int NW = 2;
@@ -359,11 +381,15 @@ struct LdsFast {
   u64 ax[MAXB], ay[MAXB], az[MAXB];
   u64 mask[MAXB * NW];  // bits j > i only
   u64 allow[8 * NW];
+  u64 kset[KCAP * NW];  // K words of the non-empty pairs
+  int32_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
   int32_t sorig[MAXB];
   int32_t sslot[MAXB];
-  int32_t toff[WG + 1];
+  int32_t segn[NWAVE];
   int32_t segpre[NWAVE + 1];
-  uint16_t plist[NWAVE * SEG];  // i | j << 7
+  int32_t cnt2[2][NWAVE];
+  uint16_t plist[NWAVE * SEG];  // i | j << 7, all upper pairs
+  uint16_t eij[KCAP];           // i | j << 7, non-empty pairs
   uint8_t scode[MAXB];
 };
 
@@ -373,8 +399,8 @@ __device__ __forceinline__ int pslot(int q, const int32_t* segpre) {
   return w * SEG + (q - segpre[w]);
 }
 
-template <int SEG>
-__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
+template <int SEG, int KCAP>
+__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG, KCAP>& L) {
   constexpr int MAXB = 128, NW = 2;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
@@ -408,25 +434,25 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
     }
     segn += tot;
   }
-  if (lane == 0) L.toff[wave] = segn;
+  if (lane == 0) L.segn[wave] = segn;
   __syncthreads();
   if (tid == 0) {
     L.segpre[0] = 0;
-    for (int w = 0; w < NWAVE; ++w) L.segpre[w + 1] = L.segpre[w] + L.toff[w];
+    for (int w = 0; w < NWAVE; ++w) L.segpre[w + 1] = L.segpre[w] + L.segn[w];
   }
-  const bool overflow = L.toff[0] > SEG || L.toff[1] > SEG || L.toff[2] > SEG || L.toff[3] > SEG;
+  const bool overflow = L.segn[0] > SEG || L.segn[1] > SEG || L.segn[2] > SEG || L.segn[3] > SEG;
   __syncthreads();
   if (overflow) return false;
   const int np = L.segpre[NWAVE];
 
-  // 3. per pair (contiguous chunk per thread): LJ for owned pairs and the
-  //    number of owned third molecules
+  // 3. per pair (contiguous chunk per thread): LJ for owned pairs; count the
+  //    non-empty pairs and their owned third molecules
   const int mp = (np + WG - 1) / WG;
   const int q0 = tid * mp < np ? tid * mp : np;
   const int q1 = q0 + mp < np ? q0 + mp : np;
   double e_lj = 0.0, w_lj = 0.0;
   long long n_pair = 0;
-  int mycnt = 0, bad = 0;
+  int myne = 0, mytr = 0, bad = 0;
   {
     int cur = -1;
     double fx = 0.0, fy = 0.0, fz = 0.0;
@@ -436,8 +462,10 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
       const int cij = L.scode[i] & L.scode[j];
       if (do_atm) {
         const u64* al = &L.allow[cij * NW];
-        mycnt += __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
-                 __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
+        const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
+                      __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
+        mytr += c;
+        myne += (c > 0);
       }
       if (do_lj && cij == 0) {
         if (i != cur) {
@@ -458,57 +486,69 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
     if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
   }
 
-  // triplet offsets per thread chunk
-  const int incl = wave_incl_scan(mycnt, lane);
-  if (lane == 63) L.h.wsum[wave] = incl;
+  // offsets of this thread's non-empty pairs and triplets
+  const int incl_e = wave_incl_scan(myne, lane);
+  const int incl_t = wave_incl_scan(mytr, lane);
+  if (lane == 63) {
+    L.cnt2[0][wave] = incl_e;
+    L.cnt2[1][wave] = incl_t;
+  }
   __syncthreads();
-  int ntr = 0, myoff = incl - mycnt;
+  int ne = 0, ntr = 0, eo = incl_e - myne, to = incl_t - mytr;
   for (int w = 0; w < NWAVE; ++w) {
-    const int v = L.h.wsum[w];
-    if (w < wave) myoff += v;
-    ntr += v;
+    const int ve = L.cnt2[0][w], vt = L.cnt2[1][w];
+    if (w < wave) {
+      eo += ve;
+      to += vt;
+    }
+    ne += ve;
+    ntr += vt;
   }
 
   double e_atm = 0.0;
   if (do_atm && ntr > 0) {
-    // 4. thread t takes triplets [t*m, (t+1)*m) of the block's order (pair
-    //    order, k ascending), starting from the chunk that holds t*m
-    L.toff[tid] = myoff;
-    if (tid == 0) L.toff[WG] = ntr;
+    if (ne > KCAP) return false;  // uniform: ne is a block total
+    // 4. compact the non-empty pairs with their K words and triplet offsets
+    for (int q = q0; q < q1; ++q) {
+      const int e = L.plist[pslot<SEG>(q, L.segpre)];
+      const int i = e & 127, j = e >> 7;
+      const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
+      const u64 K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
+      const u64 K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
+      const int c = __popcll(K0) + __popcll(K1);
+      if (c) {
+        L.kset[eo * NW + 0] = K0;
+        L.kset[eo * NW + 1] = K1;
+        L.eij[eo] = (uint16_t)e;
+        L.eoff[eo] = to;
+        ++eo;
+        to += c;
+      }
+    }
+    if (tid == 0) L.eoff[ne] = ntr;
     __syncthreads();
+
+    // 5. ATM: thread t takes triplets [t*m, (t+1)*m) in (pair, k) order
     const int m = (ntr + WG - 1) / WG;
     const int T0 = tid * m < ntr ? tid * m : ntr;
     const int T1 = T0 + m < ntr ? T0 + m : ntr;
     float eu = 0.f;
     if (T0 < T1) {
-      int lo = 0, hi = WG;  // toff[lo] <= T0 < toff[hi]
+      int lo = 0, hi = ne;  // eoff[lo] <= T0 < eoff[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (L.toff[mid] <= T0) lo = mid;
+        if (L.eoff[mid] <= T0) lo = mid;
         else hi = mid;
       }
-      int rem = T0 - L.toff[lo];
-      int q = lo * mp;
-      int i = 0, j = 0;
-      u64 K0 = 0, K1 = 0;
-      for (;;) {  // skip whole pairs
-        const int e = L.plist[pslot<SEG>(q, L.segpre)];
-        i = e & 127;
-        j = e >> 7;
-        const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-        K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
-        K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
-        const int c = __popcll(K0) + __popcll(K1);
-        if (rem < c) break;
-        rem -= c;
-        ++q;
-      }
-      for (; rem > 0; --rem) {  // skip within the pair
+      int ep = lo;
+      u64 K0 = L.kset[ep * NW + 0], K1 = L.kset[ep * NW + 1];
+      for (int rem = T0 - L.eoff[ep]; rem > 0; --rem) {
         if (K0) K0 &= K0 - 1;
         else K1 &= K1 - 1;
       }
-      float4 pi = L.sp[i], pj = L.sp[j];
-      int ci = i, cj = j;
+      int e = L.eij[ep];
+      int ci = e & 127, cj = e >> 7;
+      float4 pi = L.sp[ci], pj = L.sp[cj];
       float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f;
       for (int t = T0; t < T1; ++t) {
         int k;
@@ -528,34 +568,29 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG>& L) {
         ajx += r.fjx;
         ajy += r.fjy;
         ajz += r.fjz;
-        add_fix(L.ax, L.ay, L.az, k, -(double)(r.fix + r.fjx), -(double)(r.fiy + r.fjy), -(double)(r.fiz + r.fjz),
-                &bad);
-        if ((K0 | K1) == 0 && t + 1 < T1) {
-          do {  // next pair with a non-empty K
-            ++q;
-            const int e = L.plist[pslot<SEG>(q, L.segpre)];
-            i = e & 127;
-            j = e >> 7;
-            const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-            K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
-            K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
-          } while ((K0 | K1) == 0);
+        add_fix_f(L.ax, L.ay, L.az, k, -(r.fix + r.fjx), -(r.fiy + r.fjy), -(r.fiz + r.fjz), &bad);
+        if ((K0 | K1) == 0 && t + 1 < T1) {  // next non-empty pair
+          ++ep;
+          K0 = L.kset[ep * NW + 0];
+          K1 = L.kset[ep * NW + 1];
+          e = L.eij[ep];
+          const int i = e & 127, j = e >> 7;
           if (i != ci) {
-            add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+            add_fix_f(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
             aix = aiy = aiz = 0.f;
             ci = i;
             pi = L.sp[i];
           }
           if (j != cj) {
-            add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+            add_fix_f(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
             ajx = ajy = ajz = 0.f;
             cj = j;
             pj = L.sp[j];
           }
         }
       }
-      add_fix(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
-      add_fix(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+      add_fix_f(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
+      add_fix_f(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
     }
     e_atm = (double)eu;
   }
@@ -767,13 +802,13 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 // than a pair segment holds are queued for k_block_big.  Workgroup ids are
 // spread over the 8 XCDs round-robin; consecutive ids on one XCD map to
 // consecutive base cells so neighbouring blocks share its L2.
-template <int SEG>
+template <int SEG, int KCAP>
 __global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
-  __shared__ LdsFast<SEG> L;
+  __shared__ LdsFast<SEG, KCAP> L;
   const int per = (a.ncells + 7) / 8;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if ((blockIdx.x >> 3) >= per || b >= a.ncells) return;
-  if (!do_block_fast<SEG>(a, b, L)) {
+  if (!do_block_fast<SEG, KCAP>(a, b, L)) {
     if (threadIdx.x == 0) {
       const int q = atomicAdd(&a.defer[0], 1);
       a.defer[2 + q] = b;
@@ -975,7 +1010,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   const int per = (a.ncells + 7) / 8;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block<1024>), dim3(8 * per), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL((k_block<512, 512>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
