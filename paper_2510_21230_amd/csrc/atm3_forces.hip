@@ -224,7 +224,9 @@ __device__ __forceinline__ double lj_pair(double ex, double ey, double ez, doubl
                                           double* w_lj) {
   // 4 eps [(s/r)^12 - (s/r)^6]; F_i = 24 eps [2 (s/r)^12 - (s/r)^6] r_ij / r^2
   const double r2 = ex * ex + ey * ey + ez * ez;
-  const double ir2 = 1.0 / r2;
+  double ir2 = __builtin_amdgcn_rcp(r2);  // refined by two Newton steps
+  ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
+  ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
   const double s2 = sig2 * ir2;
   const double s6 = s2 * s2 * s2;
   const double s12 = s6 * s6;
@@ -304,23 +306,39 @@ __device__ void block_allow(int n, const uint8_t* scode, u64* allow) {
   }
 }
 
-// Upper-triangle mask word (bits j > i of word w) of row i, one wave.
+// Upper-triangle mask word (bits j > i of word w) of row i, one wave; i, w
+// and n are wave-uniform, so the lane-validity mask is scalar work.
 __device__ __forceinline__ u64 mask_word(const ForceArgs& a, int i, int w, int n, const float4 pi, const float4 pj,
                                          const int32_t* sorig) {
   const int lane = threadIdx.x & 63;
-  const int j = 64 * w + lane;
-  const bool valid = (j > i) && (j < n);
+  const int lo = i + 1 - 64 * w, hi = n - 64 * w;  // valid lanes: lo <= lane < hi
+  u64 valid = (hi >= 64) ? ~0ull : ((hi <= 0) ? 0ull : ((1ull << hi) - 1ull));
+  valid &= (lo <= 0) ? ~0ull : ((lo >= 64) ? 0ull : (~0ull << lo));
   const float ex = pi.x - pj.x, ey = pi.y - pj.y, ez = pi.z - pj.z;
-  const float r2 = valid ? ex * ex + ey * ey + ez * ez : 3.0e38f;
-  const bool in = r2 < a.lo2;
-  const bool maybe = !in && r2 < a.hi2;
-  u64 bits = __ballot(in);
-  if (__ballot(maybe)) {
+  const float r2 = ex * ex + ey * ey + ez * ez;
+  u64 bits = __ballot(r2 < a.lo2) & valid;
+  const u64 maybe = __ballot(r2 < a.hi2) & valid & ~bits;
+  if (maybe) {
     bool exq = false;
-    if (maybe) exq = exact_r2(a.pos, sorig[i], sorig[j], a.box[0], a.box[1], a.box[2]) < a.rc2;
+    if ((maybe >> lane) & 1ull) exq = exact_r2(a.pos, sorig[i], sorig[64 * w + lane], a.box[0], a.box[1], a.box[2]) < a.rc2;
     bits |= __ballot(exq);
   }
   return bits;
+}
+
+__device__ __forceinline__ float dist2f(const float4 p, const float4 q) {
+  const float ex = p.x - q.x, ey = p.y - q.y, ez = p.z - q.z;
+  return ex * ex + ey * ey + ez * ez;
+}
+
+// Exact (FP64 minimum-image) cutoff test of the lanes in `maybe` for row i,
+// word w; returns the bits that pass.
+__device__ __forceinline__ u64 exact_bits(const ForceArgs& a, int i, int w, u64 maybe, const int32_t* sorig) {
+  const int lane = threadIdx.x & 63;
+  bool in = false;
+  if ((maybe >> lane) & 1ull)
+    in = exact_r2(a.pos, sorig[i], sorig[64 * w + lane], a.box[0], a.box[1], a.box[2]) < a.rc2;
+  return __ballot(in);
 }
 
 // Per-corner partials (fixed point) and block energy / count partials.
@@ -366,15 +384,17 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
 }
 
 // ---------------------------------------------------------------------------
-// Fast path: at most 128 molecules; the upper pairs are listed in four
-// per-wave segments of SEG entries (wave w lists the rows i = w mod 4 in
-// order); the pairs with a non-empty K (about a third of them) are then
+// Fast path: at most 128 molecules.  The upper-triangle pair masks are built
+// one wave per row; one thread per mask word then lists the upper pairs
+// (PCAP at most) and the upper pairs the block owns (PCAP/2 at most) in
+// row-major order.  The pairs with a non-empty K (about a third of them) are
 // compacted with their K words and triplet offsets, at most KCAP of them.
 // ---------------------------------------------------------------------------
-template <int SEG, int KCAP>
+template <int PCAP, int KCAP>
 struct LdsFast {
   static constexpr int MAXB = 128;
   static constexpr int NW = 2;
+  static constexpr int OCAP = PCAP / 2;
   BlockHead h;
   double4 dp[MAXB];
   float4 sp[MAXB];
@@ -385,23 +405,17 @@ struct LdsFast {
   int32_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
   int32_t sorig[MAXB];
   int32_t sslot[MAXB];
-  int32_t segn[NWAVE];
-  int32_t segpre[NWAVE + 1];
   int32_t cnt2[2][NWAVE];
-  uint16_t plist[NWAVE * SEG];  // i | j << 7, all upper pairs
-  uint16_t eij[KCAP];           // i | j << 7, non-empty pairs
+  uint16_t plist[PCAP];  // i | j << 7, all upper pairs
+  uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns
+  uint16_t eij[KCAP];    // i | j << 7, non-empty pairs
   uint8_t scode[MAXB];
 };
 
-template <int SEG>
-__device__ __forceinline__ int pslot(int q, const int32_t* segpre) {
-  const int w = (q >= segpre[1]) + (q >= segpre[2]) + (q >= segpre[3]);
-  return w * SEG + (q - segpre[w]);
-}
-
-template <int SEG, int KCAP>
-__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG, KCAP>& L) {
-  constexpr int MAXB = 128, NW = 2;
+template <int PCAP, int KCAP>
+__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L) {
+  constexpr int MAXB = 128, NW = 2, OCAP = PCAP / 2;
+  static_assert(WG == MAXB * NW, "one thread per mask word");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
   const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
@@ -412,78 +426,135 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG, KCAP>& L) 
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
 
-  // 2. upper-triangle masks and the per-wave pair segments
-  const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 pj0 = (lane < n) ? L.sp[lane] : zero4;
-  const float4 pj1 = (64 + lane < n) ? L.sp[64 + lane] : zero4;
-  int segn = 0;
-  for (int i = wave; i < n; i += NWAVE) {
-    const float4 pi = L.sp[i];
-    const u64 b0 = mask_word(a, i, 0, n, pi, pj0, L.sorig);
-    const u64 b1 = mask_word(a, i, 1, n, pi, pj1, L.sorig);
-    const int c0 = __popcll(b0);
-    const int tot = c0 + __popcll(b1);
-    if (lane == 0) {
-      L.mask[i * NW + 0] = b0;
-      L.mask[i * NW + 1] = b1;
+  // 2. upper-triangle mask words, one wave per row (rows wave, wave + 4, ...).
+  //    Lanes past the last molecule hold a far-away position, so only the
+  //    triangle (j > i) has to be masked.
+  {
+    const float4 far4 = make_float4(1e18f, 1e18f, 1e18f, 0.f);
+    const float4 pj0 = (lane < n) ? L.sp[lane] : far4;
+    const float4 pj1 = (64 + lane < n) ? L.sp[64 + lane] : far4;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const int n0 = n < 63 ? n : 63;  // rows with bits in word 0
+    const bool two = n > 64;
+    int i = wv;
+    for (; i < n0; i += NWAVE) {
+      const float4 pi = L.sp[i];
+      const float r0 = dist2f(pi, pj0);
+      const float r1 = two ? dist2f(pi, pj1) : 1e30f;
+      const u64 tri = ~0ull << (i + 1);
+      u64 b0 = __ballot(r0 < a.lo2) & tri;
+      u64 b1 = __ballot(r1 < a.lo2);
+      const u64 m0 = __ballot(r0 < a.hi2) & tri & ~b0;
+      const u64 m1 = __ballot(r1 < a.hi2) & ~b1;
+      if (m0 | m1) {
+        b0 |= exact_bits(a, i, 0, m0, L.sorig);
+        b1 |= exact_bits(a, i, 1, m1, L.sorig);
+      }
+      if (lane == 0) {
+        L.mask[i * NW + 0] = b0;
+        L.mask[i * NW + 1] = b1;
+      }
     }
-    if (segn + tot <= SEG) {
-      uint16_t* seg = &L.plist[wave * SEG + segn];
-      if ((b0 >> lane) & 1ull) seg[__popcll(b0 & ((1ull << lane) - 1ull))] = (uint16_t)(i | (lane << 7));
-      if ((b1 >> lane) & 1ull) seg[c0 + __popcll(b1 & ((1ull << lane) - 1ull))] = (uint16_t)(i | ((64 + lane) << 7));
+    for (; i < n; i += NWAVE) {  // rows 63.. have bits in word 1 only
+      const float4 pi = L.sp[i];
+      const float r1 = dist2f(pi, pj1);
+      const u64 tri = ~0ull << (i - 63);
+      u64 b1 = __ballot(r1 < a.lo2) & tri;
+      const u64 m1 = __ballot(r1 < a.hi2) & tri & ~b1;
+      if (m1) b1 |= exact_bits(a, i, 1, m1, L.sorig);
+      if (lane == 0) {
+        L.mask[i * NW + 0] = 0ull;
+        L.mask[i * NW + 1] = b1;
+      }
     }
-    segn += tot;
+    for (; i < MAXB; i += NWAVE) {
+      if (lane == 0) {
+        L.mask[i * NW + 0] = 0ull;
+        L.mask[i * NW + 1] = 0ull;
+      }
+    }
   }
-  if (lane == 0) L.segn[wave] = segn;
   __syncthreads();
-  if (tid == 0) {
-    L.segpre[0] = 0;
-    for (int w = 0; w < NWAVE; ++w) L.segpre[w + 1] = L.segpre[w] + L.segn[w];
-  }
-  const bool overflow = L.segn[0] > SEG || L.segn[1] > SEG || L.segn[2] > SEG || L.segn[3] > SEG;
-  __syncthreads();
-  if (overflow) return false;
-  const int np = L.segpre[NWAVE];
 
-  // 3. per pair (contiguous chunk per thread): LJ for owned pairs; count the
-  //    non-empty pairs and their owned third molecules
+  // 3. pair lists: thread t lists the bits of mask word t (row t / 2); the
+  //    two list offsets come from one scan of (count | owned count << 16)
+  int np, no;
+  {
+    const int ri = tid >> 1, rw = tid & 1;
+    u64 wb = L.mask[tid];
+    u64 wo = (ri < n) ? (wb & L.allow[L.scode[ri] * NW + rw]) : 0ull;
+    const int packed = __popcll(wb) | (__popcll(wo) << 16);
+    const int incl = wave_incl_scan(packed, lane);
+    if (lane == 63) L.cnt2[0][wave] = incl;
+    __syncthreads();
+    int pre = incl - packed, tot = 0;
+    for (int w = 0; w < NWAVE; ++w) {
+      const int v = L.cnt2[0][w];
+      if (w < wave) pre += v;
+      tot += v;
+    }
+    np = tot & 0xffff;
+    no = tot >> 16;
+    if (np > PCAP || no > OCAP) return false;  // uniform: block totals
+    int p = pre & 0xffff, o = pre >> 16;
+    const int jb = 64 * rw;
+    while (wb) {
+      L.plist[p++] = (uint16_t)(ri | ((jb + __builtin_ctzll(wb)) << 7));
+      wb &= wb - 1ull;
+    }
+    while (wo) {
+      L.olist[o++] = (uint16_t)(ri | ((jb + __builtin_ctzll(wo)) << 7));
+      wo &= wo - 1ull;
+    }
+  }
+  __syncthreads();
+
+  double e_lj = 0.0, w_lj = 0.0;
+  long long n_pair = 0;
+  int bad = 0;
+  // 3a. LJ over the owned pairs (contiguous chunk per thread, FP64)
+  if (do_lj) {
+    const int mo = (no + WG - 1) / WG;
+    const int o0 = tid * mo < no ? tid * mo : no;
+    const int o1 = o0 + mo < no ? o0 + mo : no;
+    int cur = -1;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int q = o0; q < o1; ++q) {
+      const int e = L.olist[q];
+      const int i = e & 127, j = e >> 7;
+      if (i != cur) {
+        if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+        cur = i;
+        fx = fy = fz = 0.0;
+      }
+      const double4 di = L.dp[i], dj = L.dp[j];
+      const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
+      const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
+      fx += f * ex;
+      fy += f * ey;
+      fz += f * ez;
+      add_fix(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &bad);
+    }
+    if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+    n_pair = o1 - o0;
+  }
+
+  // 3b. per pair (contiguous chunk per thread): count the non-empty pairs and
+  //     their owned third molecules
   const int mp = (np + WG - 1) / WG;
   const int q0 = tid * mp < np ? tid * mp : np;
   const int q1 = q0 + mp < np ? q0 + mp : np;
-  double e_lj = 0.0, w_lj = 0.0;
-  long long n_pair = 0;
-  int myne = 0, mytr = 0, bad = 0;
-  {
-    int cur = -1;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
+  int myne = 0, mytr = 0;
+  if (do_atm) {
     for (int q = q0; q < q1; ++q) {
-      const int e = L.plist[pslot<SEG>(q, L.segpre)];
+      const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
-      const int cij = L.scode[i] & L.scode[j];
-      if (do_atm) {
-        const u64* al = &L.allow[cij * NW];
-        const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
-                      __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
-        mytr += c;
-        myne += (c > 0);
-      }
-      if (do_lj && cij == 0) {
-        if (i != cur) {
-          if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
-          cur = i;
-          fx = fy = fz = 0.0;
-        }
-        const double4 di = L.dp[i], dj = L.dp[j];
-        const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
-        const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
-        fx += f * ex;
-        fy += f * ey;
-        fz += f * ez;
-        add_fix(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &bad);
-        ++n_pair;
-      }
+      const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
+      const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
+                    __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
+      mytr += c;
+      myne += (c > 0);
     }
-    if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
   }
 
   // offsets of this thread's non-empty pairs and triplets
@@ -510,7 +581,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<SEG, KCAP>& L) 
     if (ne > KCAP) return false;  // uniform: ne is a block total
     // 4. compact the non-empty pairs with their K words and triplet offsets
     for (int q = q0; q < q1; ++q) {
-      const int e = L.plist[pslot<SEG>(q, L.segpre)];
+      const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
       const u64 K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
@@ -802,13 +873,13 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 // than a pair segment holds are queued for k_block_big.  Workgroup ids are
 // spread over the 8 XCDs round-robin; consecutive ids on one XCD map to
 // consecutive base cells so neighbouring blocks share its L2.
-template <int SEG, int KCAP>
+template <int PCAP, int KCAP>
 __global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
-  __shared__ LdsFast<SEG, KCAP> L;
+  __shared__ LdsFast<PCAP, KCAP> L;
   const int per = (a.ncells + 7) / 8;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if ((blockIdx.x >> 3) >= per || b >= a.ncells) return;
-  if (!do_block_fast<SEG, KCAP>(a, b, L)) {
+  if (!do_block_fast<PCAP, KCAP>(a, b, L)) {
     if (threadIdx.x == 0) {
       const int q = atomicAdd(&a.defer[0], 1);
       a.defer[2 + q] = b;
@@ -1010,7 +1081,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   const int per = (a.ncells + 7) / 8;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block<512, 512>), dim3(8 * per), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL((k_block<2048, 512>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
