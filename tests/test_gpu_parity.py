@@ -183,6 +183,45 @@ def test_larger_workloads_full(torch_cuda, orc, name):
     _say(f"  force err {err:.2e} (ATM only {err2:.2e})")
 
 
+def _candidates_3c08(cell_count, ncell):
+    """Molecule triplets of the 3c08 cell sets from the cell populations:
+    per base cell, the 2x2x2 block's corners a, b, c (3-bit offsets) with
+    a & b & c == 0, counted per eqs. (celltriplet), (twoonetriplets) and
+    (carttriplets)."""
+    nx, ny, nz = ncell
+    cnt = cell_count.reshape(nz, ny, nx).astype(np.int64)
+    pop = [np.roll(cnt, shift=(-(o >> 2), -((o >> 1) & 1), -(o & 1)), axis=(0, 1, 2)) for o in range(8)]
+    total = pop[0] * (pop[0] - 1) * (pop[0] - 2) // 6
+    for a in range(8):
+        for b in range(8):
+            if a != b and (a & b) == 0:
+                total = total + pop[a] * (pop[a] - 1) // 2 * pop[b]
+    for a in range(8):
+        for b in range(a + 1, 8):
+            for c in range(b + 1, 8):
+                if (a & b & c) == 0:
+                    total = total + pop[a] * pop[b] * pop[c]
+    return int(total.sum())
+
+
+def test_fcc1m_full_size(torch_cuda, orc):
+    """The full-size workload in the benchmark's launch configuration: every
+    molecule's force against the per-molecule oracle, exact counts, and the
+    candidate count against the counting equations."""
+    pos, box = workloads.make("fcc1m")
+    _say(f"[fcc1m] n={len(pos)}")
+    f, r = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU)
+    ref = orc.molecules(pos, box, rc=RC, nu=NU)
+    err = check_against(ref, f, r)
+    _, clin, ncell = orc.bin_cells(pos, box, RC)
+    counts = np.bincount(clin, minlength=int(np.prod(ncell)))
+    assert r["n_candidates"] == _candidates_3c08(counts, ncell)
+    f2, r2 = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU, terms=2)
+    ref2 = orc.molecules(pos, box, rc=RC, nu=NU, terms=2)
+    err2 = check_against(ref2, f2, r2, terms=2)
+    _say(f"  force err {err:.2e} (ATM only {err2:.2e}); triplets {r['n_triplets']}")
+
+
 def test_async_equals_sync_and_repeats(torch_cuda):
     import paper_2510_21230_amd as atm3
     from paper_2510_21230_amd import _lib
