@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 CPU-baseline leg of the benchmark, never by the product package.  It shares no
 code with the GPU path.  The compiled part is ``atm3_oracle.c`` (plain C, FP64,
-OpenMP), built into ``liboracle.so`` next to this file; ``mlp.py`` is the FP64
+OpenMP), built into ``liboracle.so`` next to this file; ``surrogate.py`` is the FP64
 numpy reference of the learned pair model.
 
 Citations refer to "Linked Cell Traversal Algorithms for Three-Body
