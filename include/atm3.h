@@ -161,6 +161,108 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
 int atm3_profile_enable(atm3_ctx* ctx, int enable);
 int atm3_profile_read(atm3_ctx* ctx, int phase, double* total_ms, int64_t* launches);
 
+
+/* ------------------------------------------------------------------------
+ * Learned three-body pair surrogate.
+ *
+ * The paper computes the ATM forces exactly; this model is an addition whose
+ * error is always measured against the exact evaluation above.  Per
+ * molecule i, 64 rotation-, translation- and permutation-invariant
+ * descriptors D_i are built from its neighbours j (minimum-image
+ * r_ij^2 < rc^2, the exact path's pair rule, Sec. 2): for 16 radial channels
+ * g_a(r) = exp(-((r - mu_a)/w)^2) fc(r), mu_a = 0.8 + a w,
+ * w = (rc - 0.8)/15, fc(r) = (1 + cos(pi r/rc))/2, with u_ij = (r_j - r_i)/r_ij:
+ *   S_a = sum g_a, V_a = sum g_a u, Q_a = sum g_a (u u^T - I/3),
+ *   D_raw = [S_a, |V_a|^2, Q_a:Q_a, V_a^T Q_a V_a], D = (D_raw - mean) * inv_sd.
+ * A pair MLP on x_ij = [D_i + D_j, g(r_ij)] (80 inputs, symmetric in i, j),
+ * 80 -> 128 -> 128 -> 128 -> 2 with ReLU, gives s_ij and t_ij; the
+ * three-body force is F_i = sum_j s_ij (r_i - r_j)/r_ij (Newton 3 holds
+ * exactly) and the error estimate e_i = sum_j softplus(t_ij).  Matrix
+ * products run on BF16 MFMA with FP32 accumulation.
+ *
+ * Parameters: ATM3_MLP_NPARAM FP32 values in the order
+ *   W1 [80][128] (rows: 64 descriptor inputs, then 16 radial inputs), b1[128],
+ *   W2 [128][128], b2[128], W3 [128][128], b3[128], W4 [128][2], b4[2],
+ * each matrix [input][output] row-major.  Descriptor statistics: mean[64],
+ * inv_sd[64].
+ * ---------------------------------------------------------------------- */
+#define ATM3_MLP_NPARAM 43650
+#define ATM3_MLP_NDESC 64
+
+typedef struct atm3_mlp atm3_mlp;
+
+/* Create a model on the context's device with seeded He-initialised
+ * weights (zero biases, b4 = (0, -3)) and identity statistics (mean 0,
+ * inv_sd 1).  The model holds its parameters, Adam moments and BF16 copies;
+ * use it only with the context it was created with. */
+int atm3_mlp_create(atm3_ctx* ctx, uint64_t seed, atm3_mlp** out);
+void atm3_mlp_destroy(atm3_mlp* mlp);
+
+/* Copy parameters from / to host memory (n must be ATM3_MLP_NPARAM).
+ * Setting parameters clears the Adam moments. */
+int atm3_mlp_set_params(atm3_ctx* ctx, atm3_mlp* mlp, const float* host, int64_t n);
+int atm3_mlp_get_params(atm3_ctx* ctx, atm3_mlp* mlp, float* host, int64_t n);
+
+/* Descriptor statistics from / to host memory (64 + 64 values). */
+int atm3_mlp_set_stats(atm3_ctx* ctx, atm3_mlp* mlp, const float* mean, const float* inv_sd);
+int atm3_mlp_get_stats(atm3_ctx* ctx, atm3_mlp* mlp, float* mean, float* inv_sd);
+
+/* Fit the statistics to one configuration: per-feature mean and
+ * 1/max(sd, 1e-6) of the raw descriptors (population sd, FP64 sums). */
+int atm3_mlp_fit_stats(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_t n, const double box[3],
+                       double rc);
+
+/* Forces with the surrogate three-body term.
+ *   forces    device, n*3 FP32, input order: exact LJ (pair list, FP64
+ *             arithmetic on FP32 displacements) plus, per molecule, the
+ *             surrogate three-body force, or, where e_i > err_threshold,
+ *             the exact one-sided ATM force of that molecule (all included
+ *             triplets containing it, eqs. atm, ATMGradient, forcepairs)
+ *   err_est   device, n FP32 error estimates e_i (may be NULL)
+ *   out       host result: e_lj, w_lj, n_pairs as the exact path; e_atm and
+ *             w_atm are NaN (the surrogate has no energy); n_triplets counts
+ *             the triplets the fallback evaluated
+ *   n_fallback host, number of molecules that took the exact fallback
+ * params: eps, sigma, nu, rc as for atm3_compute_forces (the pair rule).
+ * Blocks until done.  ATM3_EINVAL for fewer than 3 cells per dimension or
+ * more than 2^30 pairs. */
+int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_t n, const double box[3],
+                          const atm3_params* params, float err_threshold, float* forces, float* err_est,
+                          atm3_result* out, int64_t* n_fallback);
+
+/* Gradient of the training loss
+ *   L = mean_i |F_i - T_i|^2 + lam * mean_i (e_i - |F_i - T_i|)^2
+ * (the second target held constant) at one configuration, with F the
+ * surrogate three-body force and T = f3_target (device, n*3 FP32, input
+ * order; for example the ATM-only forces of atm3_compute_forces).
+ *   grad_dev device, ATM3_MLP_NPARAM FP32 (may be NULL: only the loss)
+ *   loss_out host, L
+ * Blocks until done. */
+int atm3_mlp_grad(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_t n, const double box[3], double rc,
+                  const float* f3_target, float lam, float* grad_dev, double* loss_out);
+
+/* One Adam step (bias-corrected) with the gradient grad_dev (device,
+ * ATM3_MLP_NPARAM FP32); refreshes the BF16 weight copies. */
+int atm3_mlp_adam(atm3_ctx* ctx, atm3_mlp* mlp, const float* grad_dev, float lr, float beta1, float beta2,
+                  float eps);
+
+/* atm3_mlp_grad followed by atm3_mlp_adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8) on the model's own gradient buffer. */
+int atm3_mlp_train_step(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_t n, const double box[3], double rc,
+                        const float* f3_target, float lam, float lr, double* loss_out);
+
+/* Inspection of one surrogate evaluation (no fallback):
+ *   pair_ij  device, 2*cap int32: input indices of each pair
+ *   st       device, 2*cap FP32: s, t of each pair
+ *   desc     device, n*64 FP32 normalised descriptors, input order
+ *   f3       device, n*3 FP32 surrogate three-body force, input order
+ *   err      device, n FP32 error estimate, input order
+ *   n_pairs  host, number of pairs (entries beyond cap are not written)
+ * Any of the device outputs may be NULL. */
+int atm3_surrogate_pairs(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_t n, const double box[3],
+                         double rc, int64_t cap, int32_t* pair_ij, float* st, float* desc, float* f3, float* err,
+                         int64_t* n_pairs);
+
 #ifdef __cplusplus
 }
 #endif

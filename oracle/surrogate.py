@@ -25,8 +25,9 @@ kernels implement the same definition:
 
 ``bf16=True`` rounds, to bfloat16 with round-to-nearest-even, exactly the
 operands the GPU feeds its BF16 matrix instructions (descriptors and W1a for
-A = D W1a; g and W1b; the layer inputs h1, h2 and W2, W3; the backward
-operands), so that the comparison with the kernels measures only
+A = D W1a; g and W1b; the layer inputs h1, h2 and W2, W3; in the backward
+pass h3 and dL/d(s,t) for the W4 gradient, the layer deltas and W2, W3, and
+dL/dA), so that the comparison with the kernels measures only
 accumulation order.  With ``bf16=False`` everything is FP64.
 """
 from __future__ import annotations
@@ -214,7 +215,7 @@ def backward(params, cache, pairs, T, lam=1.0, bf16_ops=False):
     dt = (ge[i] + ge[j]) * sigmoid(cache["t"])  # dL/dt_ij
     dout = np.stack([ds, dt], axis=1)
     grads = {}
-    grads["W4"] = cache["h3"].T @ dout
+    grads["W4"] = _q(cache["h3"], q).T @ _q(dout, q)
     grads["b4"] = dout.sum(axis=0)
     dz3 = (dout @ params["W4"].T) * (cache["z3"] > 0)
     grads["W3"] = _q(cache["h2"], q).T @ _q(dz3, q)

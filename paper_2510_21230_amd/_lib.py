@@ -30,7 +30,12 @@ EXPORTS = (
     "atm3_create", "atm3_destroy", "atm3_set_stream", "atm3_last_error", "atm3_version",
     "atm3_bin_cells", "atm3_compute_forces", "atm3_compute_forces_async",
     "atm3_profile_enable", "atm3_profile_read",
+    "atm3_mlp_create", "atm3_mlp_destroy", "atm3_mlp_set_params", "atm3_mlp_get_params",
+    "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
+    "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
 )
+MLP_NPARAM = 43650
+MLP_NDESC = 64
 PHASES = {"binning": 0, "block": 1, "big": 2, "reduce": 3}
 
 
@@ -96,6 +101,34 @@ def load():
         lib.atm3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_int64)]
         lib.atm3_profile_read.restype = ctypes.c_int
+        u64 = ctypes.c_uint64
+        fptr = ctypes.POINTER(ctypes.c_float)
+        lib.atm3_mlp_create.argtypes = [vp, u64, ctypes.POINTER(vp)]
+        lib.atm3_mlp_create.restype = ctypes.c_int
+        lib.atm3_mlp_destroy.argtypes = [vp]
+        lib.atm3_mlp_destroy.restype = None
+        for name in ("atm3_mlp_set_params", "atm3_mlp_get_params"):
+            getattr(lib, name).argtypes = [vp, vp, fptr, i64]
+            getattr(lib, name).restype = ctypes.c_int
+        for name in ("atm3_mlp_set_stats", "atm3_mlp_get_stats"):
+            getattr(lib, name).argtypes = [vp, vp, fptr, fptr]
+            getattr(lib, name).restype = ctypes.c_int
+        lib.atm3_mlp_fit_stats.argtypes = [vp, vp, vp, i64, dptr, ctypes.c_double]
+        lib.atm3_mlp_fit_stats.restype = ctypes.c_int
+        lib.atm3_surrogate_forces.argtypes = [vp, vp, vp, i64, dptr, ctypes.POINTER(Params), ctypes.c_float, vp, vp,
+                                              ctypes.POINTER(Result), ctypes.POINTER(i64)]
+        lib.atm3_surrogate_forces.restype = ctypes.c_int
+        lib.atm3_mlp_grad.argtypes = [vp, vp, vp, i64, dptr, ctypes.c_double, vp, ctypes.c_float, vp,
+                                      ctypes.POINTER(ctypes.c_double)]
+        lib.atm3_mlp_grad.restype = ctypes.c_int
+        lib.atm3_mlp_adam.argtypes = [vp, vp, vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]
+        lib.atm3_mlp_adam.restype = ctypes.c_int
+        lib.atm3_mlp_train_step.argtypes = [vp, vp, vp, i64, dptr, ctypes.c_double, vp, ctypes.c_float,
+                                            ctypes.c_float, ctypes.POINTER(ctypes.c_double)]
+        lib.atm3_mlp_train_step.restype = ctypes.c_int
+        lib.atm3_surrogate_pairs.argtypes = [vp, vp, vp, i64, dptr, ctypes.c_double, i64, vp, vp, vp, vp, vp,
+                                             ctypes.POINTER(i64)]
+        lib.atm3_surrogate_pairs.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -251,3 +284,139 @@ def compute_forces(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="p
     return context(pos.device).compute_forces(pos, box, forces=forces, rc=rc, nu=nu, eps=eps, sigma=sigma,
                                               truncation=truncation, variant=variant, terms=terms,
                                               check_finite=check_finite)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Mlp:
+    """The learned pair surrogate (parameters, Adam state, BF16 copies) on one
+    device; every computation runs in libatm3's kernels."""
+
+    def __init__(self, seed=0, device=None):
+        self.ctx = context(device)
+        self.lib = self.ctx.lib
+        h = ctypes.c_void_p()
+        self.ctx._check(self.lib.atm3_mlp_create(self.ctx.h, ctypes.c_uint64(seed), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.atm3_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(MLP_NPARAM, dtype=np.float32)
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_get_params(self.ctx.h, self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                     MLP_NPARAM))
+        return out
+
+    def set_params(self, flat):
+        import numpy as np
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters")
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_set_params(self.ctx.h, self.h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                                     MLP_NPARAM))
+
+    def get_stats(self):
+        import numpy as np
+        m = np.zeros(64, dtype=np.float32)
+        s = np.zeros(64, dtype=np.float32)
+        self.ctx._stream()
+        fp = ctypes.POINTER(ctypes.c_float)
+        self.ctx._check(self.lib.atm3_mlp_get_stats(self.ctx.h, self.h, m.ctypes.data_as(fp), s.ctypes.data_as(fp)))
+        return m, s
+
+    def set_stats(self, mean, inv_sd):
+        import numpy as np
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(inv_sd, dtype=np.float32)
+        if m.size != 64 or s.size != 64:
+            raise ValueError("statistics have 64 entries each")
+        self.ctx._stream()
+        fp = ctypes.POINTER(ctypes.c_float)
+        self.ctx._check(self.lib.atm3_mlp_set_stats(self.ctx.h, self.h, m.ctypes.data_as(fp), s.ctypes.data_as(fp)))
+
+    def fit_stats(self, pos, box, rc=2.5):
+        pos = self.ctx._pos(pos)
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_fit_stats(self.ctx.h, self.h, _ptr(pos), pos.shape[0], _box(box), float(rc)))
+
+    def forces(self, pos, box, threshold=float("inf"), rc=2.5, nu=0.073, eps=1.0, sigma=1.0, want_err=False,
+               forces=None):
+        """LJ + surrogate three-body forces (exact ATM where the error estimate
+        exceeds `threshold`); returns (forces, result dict, n_fallback, err)."""
+        import torch
+        pos = self.ctx._pos(pos)
+        n = pos.shape[0]
+        if forces is None:
+            forces = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+        err = torch.empty(n, dtype=torch.float32, device=pos.device) if want_err else None
+        p = make_params(rc=rc, nu=nu, eps=eps, sigma=sigma)
+        r = Result()
+        nf = ctypes.c_int64()
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_surrogate_forces(self.ctx.h, self.h, _ptr(pos), n, _box(box), ctypes.byref(p),
+                                                       float(threshold), _ptr(forces), _ptr(err), ctypes.byref(r),
+                                                       ctypes.byref(nf)))
+        return forces, r.as_dict(), int(nf.value), err
+
+    def grad(self, pos, box, target, lam=1.0, rc=2.5, with_grad=True):
+        """(gradient tensor or None, loss) of the training loss at one configuration."""
+        import torch
+        pos = self.ctx._pos(pos)
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=pos.device) if with_grad else None
+        loss = ctypes.c_double()
+        tgt = target.contiguous()
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_grad(self.ctx.h, self.h, _ptr(pos), pos.shape[0], _box(box), float(rc),
+                                               _ptr(tgt), float(lam), _ptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def adam(self, grad, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_adam(self.ctx.h, self.h, _ptr(grad.contiguous()), float(lr), float(beta1),
+                                               float(beta2), float(eps)))
+
+    def train_step(self, pos, box, target, lam=1.0, lr=1e-3, rc=2.5):
+        pos = self.ctx._pos(pos)
+        loss = ctypes.c_double()
+        tgt = target.contiguous()
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_mlp_train_step(self.ctx.h, self.h, _ptr(pos), pos.shape[0], _box(box),
+                                                     float(rc), _ptr(tgt), float(lam), float(lr),
+                                                     ctypes.byref(loss)))
+        return loss.value
+
+    def pairs(self, pos, box, rc=2.5, cap=None):
+        """Per-pair outputs and per-molecule descriptors / force / error
+        estimate of one evaluation, for inspection (input order)."""
+        import torch
+        pos = self.ctx._pos(pos)
+        n = pos.shape[0]
+        npairs = ctypes.c_int64()
+        self.ctx._stream()
+        self.ctx._check(self.lib.atm3_surrogate_pairs(self.ctx.h, self.h, _ptr(pos), n, _box(box), float(rc), 0,
+                                                      None, None, None, None, None, ctypes.byref(npairs)))
+        P = npairs.value if cap is None else min(cap, npairs.value)
+        dev = pos.device
+        ij = torch.empty((max(P, 1), 2), dtype=torch.int32, device=dev)
+        st = torch.empty((max(P, 1), 2), dtype=torch.float32, device=dev)
+        desc = torch.empty((n, 64), dtype=torch.float32, device=dev)
+        f3 = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        err = torch.empty(n, dtype=torch.float32, device=dev)
+        self.ctx._check(self.lib.atm3_surrogate_pairs(self.ctx.h, self.h, _ptr(pos), n, _box(box), float(rc), P,
+                                                      _ptr(ij), _ptr(st), _ptr(desc), _ptr(f3), _ptr(err),
+                                                      ctypes.byref(npairs)))
+        return {"pair_ij": ij[:P], "st": st[:P], "desc": desc, "f3": f3, "err": err, "n_pairs": npairs.value}

@@ -20,6 +20,7 @@ SOURCES = {
     "atm3_api.hip": [],
     "atm3_binning.hip": ["-ffp-contract=off"],
     "atm3_forces.hip": [],
+    "atm3_surrogate.hip": [],
 }
 
 COMMON = [

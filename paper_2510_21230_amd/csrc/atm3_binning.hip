@@ -197,4 +197,12 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
   return phase_end(ctx, ATM3_PHASE_BINNING);
 }
 
+hipError_t launch_scan(hipStream_t st, const int32_t* count, int32_t* start, int64_t n, int32_t* tile_sum) {
+  const int32_t ntiles = (int32_t)((n + TILE - 1) / TILE);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles > 0 ? ntiles : 1), dim3(256), 0, st, count, start, tile_sum, n);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
+  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256), 0, st, start, tile_sum, n, ntiles);
+  return hipGetLastError();
+}
+
 }  // namespace atm3

@@ -34,6 +34,41 @@ enum Buf {
   B_DEFER,        // int32 [C+2] [0] deferred count, [1] status, [2..] base cells
   B_RED,          // first-stage reduction partials
   B_TILE,         // int32 per-tile sums of the cell-count scan
+  // learned surrogate (atm3_surrogate.hip); slot = sorted molecule index
+  B_SN_ALL,       // int32 [N]   neighbours per slot
+  B_SN_UP,        // int32 [N]   neighbours with a larger slot
+  B_SN_START,     // int32 [N+1] first neighbour entry of each slot
+  B_SN_UPSTART,   // int32 [N+1] first pair of each slot
+  B_SN_LOFILL,    // int32 [N]   fill counters of the lower entries
+  B_SN_TILE,      // int32 scan tiles
+  B_SN_NB,        // int32 [2P]  neighbour entries: 2*pair + (slot is the pair's second)
+  B_SP_IJ,        // int2 [P]    pair slots (i < j)
+  B_SP_REC,       // float4 [P]  r_i - r_j and |r_i - r_j|
+  B_SP_ST,        // float2 [P]  pair outputs s, t
+  B_SD,           // float [N][64] descriptors (normalised, or raw when fitting)
+  B_SDB,          // bf16 [N][64]
+  B_SA,           // float [N][128] first-layer projection D W1a
+  B_SQ,           // int32 [N+1] fallback queue (count, slots)
+  B_SRED,         // double reduction partials
+  B_SF3,          // float4 [N] surrogate three-body force per slot
+  B_SE,           // float [N]  error estimate per slot
+  B_SG,           // float4 [N] dL/dF per slot
+  B_SGE,          // float [N]  dL/de per slot
+  B_TH1,          // bf16 [P][128] hidden activations (training)
+  B_TH2,
+  B_TH3,
+  B_TG16,         // bf16 [P][16] radial inputs (training)
+  B_TDOUT,        // float [P][2] dL/d(s, t)
+  B_TDOUTB,       // bf16 [P][2]
+  B_TDZ3,         // float [P][128] layer deltas
+  B_TDZ2,
+  B_TDZ1,
+  B_TDZ3B,        // bf16 [P][128]
+  B_TDZ2B,
+  B_TDZ1B,
+  B_TDA,          // float [N][128] dL/dA
+  B_TDAB,         // bf16 [N][128]
+  B_TPART,        // float split-K partial products
   B_NBUF
 };
 
@@ -83,6 +118,10 @@ bool make_grid(const double box[3], double rc, Grid* g);
 // Binning (atm3_binning.hip): fills B_CELL_OF, B_COUNT, B_START, B_PERM,
 // B_SORTED from the FP64 positions.
 hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g);
+
+// Exclusive prefix sum of count[0..n) into start[0..n], start[n] = total;
+// tile_sum needs n/1024 + 2 entries.
+hipError_t launch_scan(hipStream_t st, const int32_t* count, int32_t* start, int64_t n, int32_t* tile_sum);
 
 // Forces (atm3_forces.hip): block kernels, per-corner partial forces, final
 // gather into `forces` and the reduction into `res_dev`.

@@ -1,0 +1,1557 @@
+// Learned three-body pair surrogate on gfx950: neighbour lists, invariant
+// descriptors, the pair MLP on BF16 MFMA (inference and training), force
+// assembly with an error estimate, and the exact one-sided ATM fallback.
+//
+// Slots are the cell-sorted molecule indices of the binning step.  The
+// neighbour lists are deterministic: each slot lists its neighbours with a
+// larger slot first (in the fixed order of the 27 neighbour cells and of the
+// molecules inside a cell), then the rest by pair number; every pair is stored
+// once, as (smaller slot, larger slot).
+//
+// MFMA use.  v_mfma_f32_32x32x16_bf16: for lane l (h = l / 32) the A operand
+// holds row l % 32 and k = 8h .. 8h+7, the B operand column l % 32 and
+// k = 8h .. 8h+7, and the 16 accumulators hold column l % 32 and rows
+// 8(r/4) + 4h + (r%4), r = 0..15.  The fused pair kernel works in the
+// transposed form Z^T = W^T H^T, pairs being the columns: one wave owns 32
+// pairs end to end, and the accumulators of a layer are, after ReLU and BF16
+// conversion, directly the B operand of the next layer once the input
+// features are taken in the order those registers hold them.  The weights
+// are stored permuted to that order (k_prep), so no data moves between lanes.
+#include <math.h>
+
+#include <new>
+#include <string>
+
+#include "atm3_internal.h"
+#include "atm3_terms.h"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace atm3 {
+namespace {
+
+constexpr int NR = 16, NDESC = 64, NIN = 80, WID = 128;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * WID, OFF_W2 = OFF_B1 + WID, OFF_B2 = OFF_W2 + WID * WID,
+              OFF_W3 = OFF_B2 + WID, OFF_B3 = OFF_W3 + WID * WID, OFF_W4 = OFF_B3 + WID, OFF_B4 = OFF_W4 + WID * 2,
+              NPARAM = OFF_B4 + 2;
+static_assert(NPARAM == ATM3_MLP_NPARAM, "parameter layout");
+constexpr float R0 = 0.8f;
+constexpr float PI_F = 3.14159265358979323846f;
+constexpr int NPERM1 = 4 * 64 * 8;        // layer 1 A fragments (bf16)
+constexpr int NPERM = 4 * 4 * 2 * 64 * 8;  // layers 2, 3 A fragments (bf16)
+constexpr int MAXSPLIT = 256;
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__device__ __forceinline__ f32x16 mfma32(const bf16x8 a, const bf16x8 b, const f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float softplusf(float t) { return fmaxf(t, 0.f) + log1pf(expf(-fabsf(t))); }
+
+// --------------------------------------------------------------------------
+// neighbour lists
+// --------------------------------------------------------------------------
+struct NbArgs {
+  const double4* sorted;
+  const int32_t* start;
+  const int32_t* cell_of;
+  const double* pos;
+  int32_t nx, ny, nz, n;
+  double side[3], box[3];
+  double rc2, lo2, hi2;
+  int32_t* n_all;
+  int32_t* n_up;
+  const int32_t* nb_start;
+  const int32_t* up_start;
+  int32_t* nb;
+  int2* pij;
+  float4* prec;
+};
+
+// Visit the neighbours t != s of slot s (r_st^2 < rc^2) in the fixed order of
+// the 27 cells and the slots within a cell.  The distance comes from the
+// cell-centred FP64 records; inside a 1e-9 relative band around rc^2 the
+// decision is the exact minimum-image expression on the input positions.
+template <class F>
+__device__ __forceinline__ void for_neighbours(const NbArgs& a, int s, F&& f) {
+  const double4 me = a.sorted[s];
+  const int orig = (int)me.w;
+  const int c = a.cell_of[orig];
+  const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
+  for (int dz = -1; dz <= 1; ++dz) {
+    int uz = cz + dz;
+    uz = uz < 0 ? uz + a.nz : (uz >= a.nz ? uz - a.nz : uz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      int uy = cy + dy;
+      uy = uy < 0 ? uy + a.ny : (uy >= a.ny ? uy - a.ny : uy);
+      for (int dx = -1; dx <= 1; ++dx) {
+        int ux = cx + dx;
+        ux = ux < 0 ? ux + a.nx : (ux >= a.nx ? ux - a.nx : ux);
+        const int cc = (uz * a.ny + uy) * a.nx + ux;
+        const double ox = dx * a.side[0], oy = dy * a.side[1], oz = dz * a.side[2];
+        const int t1 = a.start[cc + 1];
+        for (int t = a.start[cc]; t < t1; ++t) {
+          if (t == s) continue;
+          const double4 o = a.sorted[t];
+          // r_s - r_t = loc_s - loc_t - offset of t's cell
+          const double ex = (me.x - o.x) - ox, ey = (me.y - o.y) - oy, ez = (me.z - o.z) - oz;
+          const double r2 = ex * ex + ey * ey + ez * ez;
+          bool in;
+          if (r2 < a.lo2) in = true;
+          else if (r2 >= a.hi2) in = false;
+          else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
+          if (in) f(t, ex, ey, ez, r2);
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_nb_count(NbArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  int all = 0, up = 0;
+  for_neighbours(a, s, [&](int t, double, double, double, double) {
+    ++all;
+    up += (t > s);
+  });
+  a.n_all[s] = all;
+  a.n_up[s] = up;
+}
+
+__global__ __launch_bounds__(256) void k_nb_fill(NbArgs a) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  int k = 0;
+  const int p0 = a.up_start[s], e0 = a.nb_start[s];
+  for_neighbours(a, s, [&](int t, double ex, double ey, double ez, double r2) {
+    if (t > s) {
+      const int pid = p0 + k;
+      a.pij[pid] = make_int2(s, t);
+      a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
+      a.nb[e0 + k] = 2 * pid;
+      ++k;
+    }
+  });
+}
+
+// Second-slot entries: appended in any order, then sorted per slot.
+__global__ __launch_bounds__(256) void k_nb_lower(const int2* __restrict__ pij, int32_t P,
+                                                  const int32_t* __restrict__ nb_start,
+                                                  const int32_t* __restrict__ n_up, int32_t* __restrict__ lo_fill,
+                                                  int32_t* __restrict__ nb) {
+  const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid >= P) return;
+  const int t = pij[pid].y;
+  const int slot = nb_start[t] + n_up[t] + atomicAdd(&lo_fill[t], 1);
+  nb[slot] = 2 * pid + 1;
+}
+
+__global__ __launch_bounds__(256) void k_nb_sort(const int32_t* __restrict__ nb_start,
+                                                 const int32_t* __restrict__ n_up, int32_t n,
+                                                 int32_t* __restrict__ nb) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int lo = nb_start[s] + n_up[s], hi = nb_start[s + 1];
+  for (int x = lo + 1; x < hi; ++x) {
+    const int v = nb[x];
+    int y = x - 1;
+    while (y >= lo && nb[y] > v) {
+      nb[y + 1] = nb[y];
+      --y;
+    }
+    nb[y + 1] = v;
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+__global__ void k_zero_f32(float* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// --------------------------------------------------------------------------
+// descriptors: four threads per slot, four radial channels each
+// --------------------------------------------------------------------------
+struct DescArgs {
+  const int32_t* nb_start;
+  const int32_t* nb;
+  const float4* prec;
+  int32_t n, raw;
+  float rc, w, inv_w;
+  const float* mean;
+  const float* inv_sd;
+  float* D;
+  bf16* Db;
+};
+
+__global__ __launch_bounds__(256) void k_desc(DescArgs a) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = gid >> 2, cg = gid & 3;
+  if (s >= a.n) return;
+  float S[4], V[4][3], Q[4][6];
+  for (int c = 0; c < 4; ++c) {
+    S[c] = 0.f;
+    for (int d = 0; d < 3; ++d) V[c][d] = 0.f;
+    for (int d = 0; d < 6; ++d) Q[c][d] = 0.f;
+  }
+  const int e1 = a.nb_start[s + 1];
+  for (int e = a.nb_start[s]; e < e1; ++e) {
+    const int v = a.nb[e];
+    const float4 d = a.prec[v >> 1];
+    // u = (r_other - r_s)/r: -(r_i - r_j)/r when s is the pair's first slot
+    const float sg = (v & 1) ? 1.f : -1.f;
+    const float ir = 1.f / d.w;
+    const float ux = sg * d.x * ir, uy = sg * d.y * ir, uz = sg * d.z * ir;
+    const float fc = 0.5f * (1.f + cosf(PI_F * d.w / a.rc));
+    const float third = 1.f / 3.f;
+    for (int c = 0; c < 4; ++c) {
+      const int ch = 4 * cg + c;
+      const float q = (d.w - (R0 + ch * a.w)) * a.inv_w;
+      const float g = expf(-q * q) * fc;
+      S[c] += g;
+      V[c][0] += g * ux;
+      V[c][1] += g * uy;
+      V[c][2] += g * uz;
+      Q[c][0] += g * (ux * ux - third);
+      Q[c][1] += g * (uy * uy - third);
+      Q[c][2] += g * (uz * uz - third);
+      Q[c][3] += g * (ux * uy);
+      Q[c][4] += g * (ux * uz);
+      Q[c][5] += g * (uy * uz);
+    }
+  }
+  for (int c = 0; c < 4; ++c) {
+    const int ch = 4 * cg + c;
+    const float vx = V[c][0], vy = V[c][1], vz = V[c][2];
+    const float xx = Q[c][0], yy = Q[c][1], zz = Q[c][2], xy = Q[c][3], xz = Q[c][4], yz = Q[c][5];
+    float f[4];
+    f[0] = S[c];
+    f[1] = vx * vx + vy * vy + vz * vz;
+    f[2] = xx * xx + yy * yy + zz * zz + 2.f * (xy * xy + xz * xz + yz * yz);
+    f[3] = vx * (xx * vx + xy * vy + xz * vz) + vy * (xy * vx + yy * vy + yz * vz) + vz * (xz * vx + yz * vy + zz * vz);
+    for (int k = 0; k < 4; ++k) {
+      const int col = 16 * k + ch;
+      const float x = a.raw ? f[k] : (f[k] - a.mean[col]) * a.inv_sd[col];
+      a.D[(int64_t)s * NDESC + col] = x;
+      if (a.Db) a.Db[(int64_t)s * NDESC + col] = (bf16)x;
+    }
+  }
+}
+
+// Column mean and 1/max(sd, 1e-6) of a [rows][64] FP32 array, FP64 sums in
+// fixed order: partial sums per block, then one block combines them.
+__global__ __launch_bounds__(256) void k_colstats_part(const float* __restrict__ D, int32_t rows, int32_t chunk,
+                                                       double* __restrict__ part) {
+  const int col = threadIdx.x & 63, sub = threadIdx.x >> 6;
+  __shared__ double s1[4][64], s2[4][64];
+  const int r0 = blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+  double a1 = 0.0, a2 = 0.0;
+  for (int r = r0 + sub; r < r1; r += 4) {
+    const double x = D[(int64_t)r * 64 + col];
+    a1 += x;
+    a2 += x * x;
+  }
+  s1[sub][col] = a1;
+  s2[sub][col] = a2;
+  __syncthreads();
+  if (sub == 0) {
+    part[(int64_t)blockIdx.x * 128 + col] = ((s1[0][col] + s1[1][col]) + s1[2][col]) + s1[3][col];
+    part[(int64_t)blockIdx.x * 128 + 64 + col] = ((s2[0][col] + s2[1][col]) + s2[2][col]) + s2[3][col];
+  }
+}
+
+__global__ void k_colstats_final(const double* __restrict__ part, int32_t nparts, int32_t rows,
+                                 float* __restrict__ stats) {
+  const int col = threadIdx.x;
+  if (col >= 64) return;
+  double a1 = 0.0, a2 = 0.0;
+  for (int b = 0; b < nparts; ++b) {
+    a1 += part[(int64_t)b * 128 + col];
+    a2 += part[(int64_t)b * 128 + 64 + col];
+  }
+  const double m = a1 / rows;
+  double var = a2 / rows - m * m;
+  if (var < 0.0) var = 0.0;
+  const double sd = sqrt(var);
+  stats[col] = (float)m;
+  stats[64 + col] = (float)(1.0 / (sd > 1e-6 ? sd : 1e-6));
+}
+
+// --------------------------------------------------------------------------
+// generic BF16 MFMA product: C[m][n] = sum_k A(m,k) B(k,n) over the k range of
+// blockIdx.z, with strided operands; one wave per 32 x 32 output block, four
+// waves per workgroup along m (blockIdx.x: m, blockIdx.y: n).  Epilogue: bias, ReLU, ReLU'-mask, FP32 and/or
+// BF16 stores.
+// --------------------------------------------------------------------------
+struct GemmArgs {
+  const bf16* A;
+  int64_t sam, sak;
+  const bf16* B;
+  int64_t sbk, sbn;
+  int32_t M, N, K, kchunk;
+  float* C;
+  int64_t scm, scn, scz;
+  bf16* Cb;
+  int64_t sbm2, sbn2;
+  const float* bias;
+  const bf16* mask;
+  int64_t smm, smn;
+  int32_t relu;
+};
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m0 = (blockIdx.x * 4 + wave) * 32, n0 = blockIdx.y * 32;
+  if (m0 >= a.M) return;  // wave-uniform; no barriers below
+  const int kb = blockIdx.z * a.kchunk;
+  const int ke = min(a.K, kb + a.kchunk);
+  const int h = lane >> 5, row = m0 + (lane & 31), col = n0 + (lane & 31);
+  f32x16 acc = {};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    bf16x8 av, bv;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = k0 + 8 * h + e;
+      av[e] = (row < a.M && k < ke) ? a.A[row * a.sam + k * a.sak] : (bf16)0.f;
+      bv[e] = (col < a.N && k < ke) ? a.B[k * a.sbk + col * a.sbn] : (bf16)0.f;
+    }
+    acc = mfma32(av, bv, acc);
+  }
+  const int n = n0 + (lane & 31);
+  if (n >= a.N) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + 8 * (r >> 2) + 4 * h + (r & 3);
+    if (m >= a.M) continue;
+    float v = acc[r];
+    if (a.bias) v += a.bias[n];
+    if (a.relu) v = fmaxf(v, 0.f);
+    if (a.mask && !((float)a.mask[m * a.smm + n * a.smn] > 0.f)) v = 0.f;
+    if (a.C) a.C[blockIdx.z * a.scz + m * a.scm + n * a.scn] = v;
+    if (a.Cb) a.Cb[m * a.sbm2 + n * a.sbn2] = (bf16)v;
+  }
+}
+
+// out[i] = sum over z of part[z * stride + i], fixed order.
+__global__ __launch_bounds__(256) void k_sum_parts(const float* __restrict__ part, int32_t nz, int64_t stride,
+                                                   int64_t count, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = 0.f;
+  for (int z = 0; z < nz; ++z) s += part[z * stride + i];
+  out[i] = s;
+}
+
+// Column sums of a [rows][cols] FP32 array (cols <= 256): per-block partial
+// rows, then a fixed-order sum.
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ X, int32_t rows, int32_t cols,
+                                                     int32_t chunk, float* __restrict__ part) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.x * chunk, r1 = min(rows, r0 + chunk);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) s += X[(int64_t)r * cols + c];
+  part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+// --------------------------------------------------------------------------
+// weights: BF16 copies and the permuted MFMA fragments of the fused kernel
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prep(const float* __restrict__ P, bf16* __restrict__ w1b,
+                                              bf16* __restrict__ w2b, bf16* __restrict__ w3b,
+                                              bf16* __restrict__ wp1, bf16* __restrict__ wp2,
+                                              bf16* __restrict__ wp3) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < NIN * WID) w1b[idx] = (bf16)P[OFF_W1 + idx];
+  if (idx < WID * WID) {
+    w2b[idx] = (bf16)P[OFF_W2 + idx];
+    w3b[idx] = (bf16)P[OFF_W3 + idx];
+  }
+  if (idx < NPERM1) {
+    // [ob][lane][e]: W1b[k = 8h + e][out = 32 ob + lane % 32]
+    const int e = idx & 7, lane = (idx >> 3) & 63, ob = idx >> 9;
+    const int k = 8 * (lane >> 5) + e, out = 32 * ob + (lane & 31);
+    wp1[idx] = (bf16)P[OFF_W1 + (NDESC + k) * WID + out];
+  }
+  if (idx < NPERM) {
+    // [ob][b][ks][lane][e]: input feature 32b + 16ks + 8(e/4) + 4h + e%4
+    const int e = idx & 7, lane = (idx >> 3) & 63, ks = (idx >> 9) & 1, b = (idx >> 10) & 3, ob = idx >> 12;
+    const int f = 32 * b + 16 * ks + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    const int out = 32 * ob + (lane & 31);
+    wp2[idx] = (bf16)P[OFF_W2 + f * WID + out];
+    wp3[idx] = (bf16)P[OFF_W3 + f * WID + out];
+  }
+}
+
+// --------------------------------------------------------------------------
+// fused pair MLP (persistent; weights in LDS; one wave per 32 pairs)
+// --------------------------------------------------------------------------
+struct PairArgs {
+  const int2* pij;
+  const float4* prec;
+  const float* A;  // [slot][128]
+  const bf16* wp1;
+  const bf16* wp2;
+  const bf16* wp3;
+  const float* P;
+  int32_t np;
+  float rc, w, inv_w;
+  float2* st;
+  bf16* h1;  // training dumps [pair][128] (or NULL)
+  bf16* h2;
+  bf16* h3;
+  bf16* g16;  // [pair][16]
+};
+
+__device__ __forceinline__ void dump4(bf16* dst, const f32x16& v, int base_reg) {
+  // four consecutive features from registers base_reg .. base_reg+3 (after ReLU)
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 t;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) t[q] = (bf16)fmaxf(v[base_reg + q], 0.f);
+  *(bf16x4*)dst = t;
+}
+
+__global__ __launch_bounds__(256) void k_pair_mlp(PairArgs a) {
+  __shared__ bf16x8 w1s[4 * 64];
+  __shared__ bf16x8 w2s[32 * 64];
+  __shared__ bf16x8 w3s[32 * 64];
+  __shared__ float bsh[3 * WID];
+  __shared__ float w4s[2 * WID];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < 4 * 64; q += 256) w1s[q] = ((const bf16x8*)a.wp1)[q];
+  for (int q = tid; q < 32 * 64; q += 256) {
+    w2s[q] = ((const bf16x8*)a.wp2)[q];
+    w3s[q] = ((const bf16x8*)a.wp3)[q];
+  }
+  for (int q = tid; q < WID; q += 256) {
+    bsh[q] = a.P[OFF_B1 + q];
+    bsh[WID + q] = a.P[OFF_B2 + q];
+    bsh[2 * WID + q] = a.P[OFF_B3 + q];
+  }
+  for (int q = tid; q < 2 * WID; q += 256) w4s[q] = a.P[OFF_W4 + q];
+  const float b40 = a.P[OFF_B4], b41 = a.P[OFF_B4 + 1];
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, cn = lane & 31;
+  const float4* A4 = (const float4*)a.A;
+  const int ntiles = (a.np + 31) / 32;
+  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+    // keeps the weight fragments in LDS: without it the loop-invariant LDS
+    // reads are hoisted out of the tile loop into (spilled) registers
+    asm volatile("" ::: "memory");
+    const int p = tile * 32 + cn;
+    const bool valid = p < a.np;
+    int i = 0, j = 0;
+    float4 d = make_float4(0.f, 0.f, 0.f, 1.f);
+    if (valid) {
+      const int2 ij = a.pij[p];
+      i = ij.x;
+      j = ij.y;
+      d = a.prec[p];
+    }
+    // radial inputs, channels 8h .. 8h+7
+    const float fc = valid ? 0.5f * (1.f + cosf(PI_F * d.w / a.rc)) : 0.f;
+    bf16x8 gb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float q = (d.w - (R0 + (8 * h + e) * a.w)) * a.inv_w;
+      gb[e] = (bf16)(expf(-q * q) * fc);
+    }
+    if (a.g16 && valid) *(bf16x8*)(a.g16 + (int64_t)p * 16 + 8 * h) = gb;
+
+    // layer 1: Z1^T = W1b^T G^T + (A_i + A_j + b1)
+    f32x16 acc[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int f0 = 32 * ob + 8 * q + 4 * h;
+        float4 s4 = make_float4(bsh[f0], bsh[f0 + 1], bsh[f0 + 2], bsh[f0 + 3]);
+        if (valid) {
+          const float4 ai = A4[(int64_t)i * 32 + (f0 >> 2)], aj = A4[(int64_t)j * 32 + (f0 >> 2)];
+          s4.x += ai.x + aj.x;
+          s4.y += ai.y + aj.y;
+          s4.z += ai.z + aj.z;
+          s4.w += ai.w + aj.w;
+        }
+        acc[ob][4 * q + 0] = s4.x;
+        acc[ob][4 * q + 1] = s4.y;
+        acc[ob][4 * q + 2] = s4.z;
+        acc[ob][4 * q + 3] = s4.w;
+      }
+      acc[ob] = mfma32(w1s[ob * 64 + lane], gb, acc[ob]);
+    }
+
+    // layers 2 and 3
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+      bf16x8 hb[4][2];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)fmaxf(acc[b][8 * ks + e], 0.f);
+      bf16* dump = layer == 0 ? a.h1 : a.h2;
+      if (dump && valid) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dump4(dump + (int64_t)p * WID + 32 * b + 8 * q + 4 * h, acc[b], 4 * q);
+      }
+      const bf16x8* ws = layer == 0 ? w2s : w3s;
+      const float* bl = bsh + (layer + 1) * WID;
+#pragma unroll
+      for (int ob = 0; ob < 4; ++ob) {
+        f32x16 c;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) c[r] = bl[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int ks = 0; ks < 2; ++ks) c = mfma32(ws[((ob * 4 + b) * 2 + ks) * 64 + lane], hb[b][ks], c);
+        acc[ob] = c;
+      }
+    }
+
+    // output layer (FP32): s, t = W4^T relu(z3) + b4
+    float ps = 0.f, pt = 0.f;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int f = 32 * ob + 8 * (r >> 2) + 4 * h + (r & 3);
+        const float v = fmaxf(acc[ob][r], 0.f);
+        ps = fmaf(w4s[2 * f], v, ps);
+        pt = fmaf(w4s[2 * f + 1], v, pt);
+      }
+    if (a.h3 && valid) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dump4(a.h3 + (int64_t)p * WID + 32 * b + 8 * q + 4 * h, acc[b], 4 * q);
+    }
+    ps += __shfl_xor(ps, 32);
+    pt += __shfl_xor(pt, 32);
+    if (h == 0 && valid) a.st[p] = make_float2(ps + b40, pt + b41);
+  }
+}
+
+// --------------------------------------------------------------------------
+// per-molecule force assembly
+// --------------------------------------------------------------------------
+struct MolArgs {
+  const int32_t* nb_start;
+  const int32_t* nb;
+  const float4* prec;
+  const float2* st;
+  const double4* sorted;
+  int32_t n, with_lj;
+  double sig2, eps24;
+  float thr;
+  float* forces;   // input order (or NULL)
+  float* err_out;  // input order (or NULL)
+  float4* f3s;     // slot order surrogate force (or NULL)
+  float* es;       // slot order error estimate (or NULL)
+  int32_t* queue;  // [0] count, [1..] slots (or NULL: no fallback)
+  double* red;     // per block: sum (s12 - s6), sum (2 s12 - s6)
+};
+
+__global__ __launch_bounds__(256) void k_mol(MolArgs a) {
+  __shared__ double r0[4], r1[4];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double elj = 0.0, wlj = 0.0;
+  if (s < a.n) {
+    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
+    double lx = 0.0, ly = 0.0, lz = 0.0;
+    const int e1 = a.nb_start[s + 1];
+    for (int q = a.nb_start[s]; q < e1; ++q) {
+      const int v = a.nb[q];
+      const int pid = v >> 1;
+      const float4 d = a.prec[pid];
+      const float2 o = a.st[pid];
+      const float sg = (v & 1) ? -1.f : 1.f;  // r_s - r_other = sg * (r_i - r_j)
+      const float k = sg * o.x / d.w;
+      fx = fmaf(k, d.x, fx);
+      fy = fmaf(k, d.y, fy);
+      fz = fmaf(k, d.z, fz);
+      e += softplusf(o.y);
+      if (a.with_lj) {
+        const double dx = (double)d.x, dy = (double)d.y, dz = (double)d.z;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double s2 = a.sig2 / r2;
+        const double s6 = s2 * s2 * s2, s12 = s6 * s6;
+        const double f = a.eps24 * (2.0 * s12 - s6) / r2 * (double)sg;
+        lx += f * dx;
+        ly += f * dy;
+        lz += f * dz;
+        if (!(v & 1)) {
+          elj += s12 - s6;
+          wlj += 2.0 * s12 - s6;
+        }
+      }
+    }
+    const int orig = (int)a.sorted[s].w;
+    const bool fall = a.queue && e > a.thr;
+    if (a.forces) {
+      a.forces[3 * (int64_t)orig + 0] = (float)(lx + (fall ? 0.0 : (double)fx));
+      a.forces[3 * (int64_t)orig + 1] = (float)(ly + (fall ? 0.0 : (double)fy));
+      a.forces[3 * (int64_t)orig + 2] = (float)(lz + (fall ? 0.0 : (double)fz));
+    }
+    if (a.err_out) a.err_out[orig] = e;
+    if (a.f3s) a.f3s[s] = make_float4(fx, fy, fz, 0.f);
+    if (a.es) a.es[s] = e;
+    if (fall) {
+      const int qq = atomicAdd(&a.queue[0], 1);
+      a.queue[1 + qq] = s;
+    }
+  }
+  if (a.red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+      elj += __shfl_xor(elj, off);
+      wlj += __shfl_xor(wlj, off);
+    }
+    if (lane == 0) {
+      r0[wave] = elj;
+      r1[wave] = wlj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.red[2 * blockIdx.x + 0] = ((r0[0] + r0[1]) + r0[2]) + r0[3];
+      a.red[2 * blockIdx.x + 1] = ((r1[0] + r1[1]) + r1[2]) + r1[3];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// exact one-sided ATM force of the queued molecules (one wave each)
+// --------------------------------------------------------------------------
+struct FallArgs {
+  const int32_t* queue;
+  const int32_t* nb_start;
+  const int32_t* nb;
+  const int2* pij;
+  const float4* prec;
+  const double4* sorted;
+  const double* pos;
+  double box[3];
+  double rc2;
+  float lo2, hi2;
+  float k3nu, k15nu, k075nu;
+  float* forces;
+  unsigned long long* ntrip;
+};
+
+__global__ __launch_bounds__(256) void k_fallback(FallArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nq = a.queue[0];
+  unsigned long long cnt_total = 0;
+  for (int qi = blockIdx.x * 4 + wave; qi < nq; qi += gridDim.x * 4) {
+    const int s = a.queue[1 + qi];
+    const int b0 = a.nb_start[s];
+    const int m = a.nb_start[s + 1] - b0;
+    const long long T = (long long)m * (m - 1) / 2;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    unsigned cnt = 0;
+    const float4 ps = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (long long q = lane; q < T; q += 64) {
+      // (x, y), x < y: row x holds m-1-x pairs
+      int x = (int)((2.0 * m - 1.0 - sqrt((2.0 * m - 1.0) * (2.0 * m - 1.0) - 8.0 * (double)q)) * 0.5);
+      if (x < 0) x = 0;
+      while (x > 0 && (long long)x * (2 * m - x - 1) / 2 > q) --x;
+      while ((long long)(x + 1) * (2 * m - x - 2) / 2 <= q) ++x;
+      const int y = (int)(q - (long long)x * (2 * m - x - 1) / 2) + x + 1;
+      const int va = a.nb[b0 + x], vb = a.nb[b0 + y];
+      const float4 da = a.prec[va >> 1], db = a.prec[vb >> 1];
+      const float sa = (va & 1) ? 1.f : -1.f, sb = (vb & 1) ? 1.f : -1.f;  // r_other - r_s
+      const float4 pj = make_float4(sa * da.x, sa * da.y, sa * da.z, 0.f);
+      const float4 pk = make_float4(sb * db.x, sb * db.y, sb * db.z, 0.f);
+      const float ex = pj.x - pk.x, ey = pj.y - pk.y, ez = pj.z - pk.z;
+      const float z = ex * ex + ey * ey + ez * ez;
+      bool in = z < a.lo2;
+      if (!in && z < a.hi2) {
+        const int2 pa = a.pij[va >> 1], pb = a.pij[vb >> 1];
+        const int ta = (va & 1) ? pa.x : pa.y, tb = (vb & 1) ? pb.x : pb.y;
+        in = exact_r2(a.pos, (int)a.sorted[ta].w, (int)a.sorted[tb].w, a.box[0], a.box[1], a.box[2]) < a.rc2;
+      }
+      if (in) {
+        const Trip r = atm_triplet(ps, pj, pk, a.k3nu, a.k15nu, a.k075nu);
+        fx += (double)r.fix;
+        fy += (double)r.fiy;
+        fz += (double)r.fiz;
+        ++cnt;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      fx += __shfl_xor(fx, off);
+      fy += __shfl_xor(fy, off);
+      fz += __shfl_xor(fz, off);
+      cnt += __shfl_xor(cnt, off);
+    }
+    if (lane == 0) {
+      const int64_t orig = (int64_t)a.sorted[s].w;
+      a.forces[3 * orig + 0] += (float)fx;
+      a.forces[3 * orig + 1] += (float)fy;
+      a.forces[3 * orig + 2] += (float)fz;
+      cnt_total += cnt;
+    }
+  }
+  if (lane == 0 && cnt_total) atomicAdd(a.ntrip, cnt_total);
+}
+
+// --------------------------------------------------------------------------
+// training
+// --------------------------------------------------------------------------
+struct LossArgs {
+  const float4* f3s;
+  const float* es;
+  const float* target;  // input order [n][3]
+  const double4* sorted;
+  int32_t n;
+  float lam, inv_n;
+  float4* gF;
+  float* ge;
+  double* red;  // per block loss partial
+};
+
+__global__ __launch_bounds__(256) void k_loss(LossArgs a) {
+  __shared__ double r0[4];
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  double l = 0.0;
+  if (s < a.n) {
+    const int64_t orig = (int64_t)a.sorted[s].w;
+    const float4 F = a.f3s[s];
+    const float dx = F.x - a.target[3 * orig], dy = F.y - a.target[3 * orig + 1], dz = F.z - a.target[3 * orig + 2];
+    const float q2 = dx * dx + dy * dy + dz * dz;
+    const float nrm = sqrtf(q2);
+    const float de = a.es[s] - nrm;
+    a.gF[s] = make_float4(2.f * dx * a.inv_n, 2.f * dy * a.inv_n, 2.f * dz * a.inv_n, 0.f);
+    a.ge[s] = 2.f * a.lam * de * a.inv_n;
+    l = (double)q2 + (double)a.lam * (double)de * (double)de;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+  if (lane == 0) r0[wave] = l;
+  __syncthreads();
+  if (threadIdx.x == 0) a.red[blockIdx.x] = ((r0[0] + r0[1]) + r0[2]) + r0[3];
+}
+
+// dL/d(s, t) per pair and the output-layer delta dz3 = (W4 dout) * (h3 > 0);
+// 32 threads per pair, four features each.
+struct DoutArgs {
+  const int2* pij;
+  const float4* prec;
+  const float2* st;
+  const float4* gF;
+  const float* ge;
+  const bf16* h3;
+  const float* P;
+  int32_t np;
+  float* dout;
+  bf16* doutb;
+  float* dz3;
+  bf16* dz3b;
+};
+
+__global__ __launch_bounds__(256) void k_dout(DoutArgs a) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = gid >> 5;
+  const int fg = gid & 31;
+  if (p >= a.np) return;
+  const int2 ij = a.pij[p];
+  const float4 d = a.prec[p];
+  const float ir = 1.f / d.w;
+  const float4 gi = a.gF[ij.x], gj = a.gF[ij.y];
+  const float ds = ((gi.x - gj.x) * d.x + (gi.y - gj.y) * d.y + (gi.z - gj.z) * d.z) * ir;
+  const float t = a.st[p].y;
+  const float sig = 1.f / (1.f + expf(-t));
+  const float dt = (a.ge[ij.x] + a.ge[ij.y]) * sig;
+  if (fg == 0) {
+    a.dout[2 * p] = ds;
+    a.dout[2 * p + 1] = dt;
+    a.doutb[2 * p] = (bf16)ds;
+    a.doutb[2 * p + 1] = (bf16)dt;
+  }
+  for (int q = 0; q < 4; ++q) {
+    const int f = 4 * fg + q;
+    float v = a.P[OFF_W4 + 2 * f] * ds + a.P[OFF_W4 + 2 * f + 1] * dt;
+    if (!((float)a.h3[p * WID + f] > 0.f)) v = 0.f;
+    a.dz3[p * WID + f] = v;
+    a.dz3b[p * WID + f] = (bf16)v;
+  }
+}
+
+// dA_s = sum of dz1 over the slot's pairs (entry order), 32 threads per slot.
+__global__ __launch_bounds__(256) void k_dA(const int32_t* __restrict__ nb_start, const int32_t* __restrict__ nb,
+                                            const float* __restrict__ dz1, int32_t n, float* __restrict__ dA,
+                                            bf16* __restrict__ dAb) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s = gid >> 5;
+  const int fg = gid & 31;
+  if (s >= n) return;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const int e1 = nb_start[s + 1];
+  for (int e = nb_start[s]; e < e1; ++e) {
+    const float4 v = ((const float4*)dz1)[(int64_t)(nb[e] >> 1) * 32 + fg];
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  ((float4*)dA)[s * 32 + fg] = acc;
+  bf16* o = dAb + s * WID + 4 * fg;
+  o[0] = (bf16)acc.x;
+  o[1] = (bf16)acc.y;
+  o[2] = (bf16)acc.z;
+  o[3] = (bf16)acc.w;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int32_t count, float lr, float b1,
+                                              float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Fixed-order sum of per-block FP64 partials (cols interleaved) into out.
+__global__ void k_sum_rows(const double* __restrict__ part, int32_t rows, int32_t cols, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= cols) return;
+  double s = 0.0;
+  for (int r = 0; r < rows; ++r) s += part[(int64_t)r * cols + c];
+  out[c] = s;
+}
+
+}  // namespace
+}  // namespace atm3
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+using namespace atm3;
+
+struct atm3_mlp {
+  int device = 0;
+  float* params = nullptr;  // [NPARAM] FP32 masters
+  float* m = nullptr;       // Adam moments
+  float* v = nullptr;
+  float* grad = nullptr;    // own gradient buffer
+  float* stats = nullptr;   // mean[64], inv_sd[64]
+  bf16* w1b = nullptr;
+  bf16* w2b = nullptr;
+  bf16* w3b = nullptr;
+  bf16* wp1 = nullptr;
+  bf16* wp2 = nullptr;
+  bf16* wp3 = nullptr;
+  double* dsum = nullptr;   // small device reduction outputs
+  int64_t step = 0;
+};
+
+namespace {
+
+// splitmix64 (Steele, Lea, Flood) and Box-Muller for the seeded initial weights
+uint64_t splitmix64(uint64_t* s) {
+  uint64_t z = (*s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double unit_open(uint64_t* s) { return ((double)(splitmix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+double normal(uint64_t* s) {
+  const double u1 = unit_open(s), u2 = unit_open(s);
+  return sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+}
+
+hipError_t prep_weights(atm3_ctx* ctx, atm3_mlp* m) {
+  hipLaunchKernelGGL(k_prep, dim3(blocks_for(NPERM > NIN * WID ? NPERM : NIN * WID, 256)), dim3(256), 0,
+                     ctx->stream, m->params, m->w1b, m->w2b, m->w3b, m->wp1, m->wp2, m->wp3);
+  return hipGetLastError();
+}
+
+int begin(atm3_ctx* ctx, atm3_mlp* m) {
+  if (!ctx || !m) return ATM3_EINVAL;
+  ctx->err.clear();
+  if (m->device != ctx->device) return fail(ctx, ATM3_EINVAL, "model and context are on different devices");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  return ATM3_OK;
+}
+
+// Geometry of one surrogate evaluation, after sur_prepare.
+struct SurGeom {
+  Grid g;
+  int64_t n = 0;
+  int64_t np = 0;
+  double rc = 0.0;
+};
+
+template <class T>
+T* buf(atm3_ctx* ctx, Buf b) {
+  return (T*)ctx->s.p[b];
+}
+
+// Binning, neighbour lists, descriptors and the first-layer projection A.
+int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double* box, double rc, bool raw,
+                SurGeom* G) {
+  if (!pos) return fail(ctx, ATM3_EINVAL, "pos is NULL");
+  if (n < 1 || n > (int64_t)1 << 26) return fail(ctx, ATM3_EINVAL, "n must be in [1, 2^26]");
+  if (!box) return fail(ctx, ATM3_EINVAL, "box is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0) || !isfinite(box[d])) return fail(ctx, ATM3_EINVAL, "box lengths must be finite and > 0");
+  if (!(rc > R0 + 0.1) || !isfinite(rc)) return fail(ctx, ATM3_EINVAL, "rc must be finite and > 0.9");
+  if (!make_grid(box, rc, &G->g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range");
+  for (int d = 0; d < 3; ++d)
+    if (G->g.n[d] < 3)
+      return fail(ctx, ATM3_EINVAL, "box too small: floor(L/rc) = " + std::to_string(G->g.n[d]) + " < 3 cells");
+  G->n = n;
+  G->rc = rc;
+  const size_t N = (size_t)n, C = (size_t)G->g.ncells;
+  int r;
+  if ((r = ensure(ctx, B_CELL_OF, 4 * N))) return r;
+  if ((r = ensure(ctx, B_RANK, 4 * N))) return r;
+  if ((r = ensure(ctx, B_COUNT, 4 * C))) return r;
+  if ((r = ensure(ctx, B_START, 4 * (C + 1)))) return r;
+  if ((r = ensure(ctx, B_PERM, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SORTED, 32 * N))) return r;
+  if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
+  if ((r = ensure(ctx, B_SN_ALL, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SN_UP, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SN_START, 4 * (N + 1)))) return r;
+  if ((r = ensure(ctx, B_SN_UPSTART, 4 * (N + 1)))) return r;
+  if ((r = ensure(ctx, B_SN_LOFILL, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SN_TILE, 4 * (N / 1024 + 2)))) return r;
+  if ((r = ensure(ctx, B_SD, 4 * 64 * N))) return r;
+  if ((r = ensure(ctx, B_SDB, 2 * 64 * N))) return r;
+  if ((r = ensure(ctx, B_SA, 4 * 128 * N))) return r;
+  hipStream_t st = ctx->stream;
+  hipError_t e = launch_binning(ctx, pos, n, G->g);
+  if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
+
+  NbArgs a;
+  a.sorted = buf<double4>(ctx, B_SORTED);
+  a.start = buf<int32_t>(ctx, B_START);
+  a.cell_of = buf<int32_t>(ctx, B_CELL_OF);
+  a.pos = pos;
+  a.nx = G->g.n[0];
+  a.ny = G->g.n[1];
+  a.nz = G->g.n[2];
+  a.n = (int32_t)n;
+  for (int d = 0; d < 3; ++d) {
+    a.side[d] = G->g.side[d];
+    a.box[d] = box[d];
+  }
+  a.rc2 = rc * rc;
+  a.lo2 = a.rc2 * (1.0 - 1e-9);
+  a.hi2 = a.rc2 * (1.0 + 1e-9);
+  a.n_all = buf<int32_t>(ctx, B_SN_ALL);
+  a.n_up = buf<int32_t>(ctx, B_SN_UP);
+  a.nb_start = buf<int32_t>(ctx, B_SN_START);
+  a.up_start = buf<int32_t>(ctx, B_SN_UPSTART);
+  hipLaunchKernelGGL(k_nb_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+  if ((e = launch_scan(st, a.n_all, buf<int32_t>(ctx, B_SN_START), n, buf<int32_t>(ctx, B_SN_TILE))) != hipSuccess)
+    return hip_fail(ctx, e, "scan");
+  if ((e = launch_scan(st, a.n_up, buf<int32_t>(ctx, B_SN_UPSTART), n, buf<int32_t>(ctx, B_SN_TILE))) != hipSuccess)
+    return hip_fail(ctx, e, "scan");
+  int32_t tot[2];
+  e = hipMemcpyAsync(&tot[0], buf<int32_t>(ctx, B_SN_UPSTART) + n, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&tot[1], buf<int32_t>(ctx, B_SN_START) + n, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "pair count");
+  const int64_t P = tot[0];
+  if (P < 0 || P >= ((int64_t)1 << 30) || tot[1] != 2 * tot[0])
+    return fail(ctx, ATM3_EINVAL, "too many neighbour pairs for 32-bit lists");
+  G->np = P;
+  if ((r = ensure(ctx, B_SN_NB, 4 * (size_t)(2 * P)))) return r;
+  if ((r = ensure(ctx, B_SP_IJ, 8 * (size_t)P))) return r;
+  if ((r = ensure(ctx, B_SP_REC, 16 * (size_t)P))) return r;
+  if ((r = ensure(ctx, B_SP_ST, 8 * (size_t)P))) return r;
+  a.nb = buf<int32_t>(ctx, B_SN_NB);
+  a.pij = buf<int2>(ctx, B_SP_IJ);
+  a.prec = buf<float4>(ctx, B_SP_REC);
+  hipLaunchKernelGGL(k_nb_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256) < 4096 ? blocks_for(n, 256) : 4096), dim3(256), 0, st,
+                     buf<int32_t>(ctx, B_SN_LOFILL), n);
+  if (P > 0)
+    hipLaunchKernelGGL(k_nb_lower, dim3(blocks_for(P, 256)), dim3(256), 0, st, a.pij, (int32_t)P, a.nb_start,
+                       a.n_up, buf<int32_t>(ctx, B_SN_LOFILL), a.nb);
+  hipLaunchKernelGGL(k_nb_sort, dim3(blocks_for(n, 256)), dim3(256), 0, st, a.nb_start, a.n_up, (int32_t)n, a.nb);
+
+  DescArgs da;
+  da.nb_start = a.nb_start;
+  da.nb = a.nb;
+  da.prec = a.prec;
+  da.n = (int32_t)n;
+  da.raw = raw ? 1 : 0;
+  da.rc = (float)rc;
+  da.w = (float)((rc - R0) / (NR - 1));
+  da.inv_w = (float)((NR - 1) / (rc - R0));
+  da.mean = m->stats;
+  da.inv_sd = m->stats + 64;
+  da.D = buf<float>(ctx, B_SD);
+  da.Db = buf<bf16>(ctx, B_SDB);
+  hipLaunchKernelGGL(k_desc, dim3(blocks_for(4 * n, 256)), dim3(256), 0, st, da);
+  if (!raw) {
+    GemmArgs ga = {};
+    ga.A = da.Db;
+    ga.sam = 64;
+    ga.sak = 1;
+    ga.B = m->w1b;  // rows 0..63 of W1, [k][n]
+    ga.sbk = 128;
+    ga.sbn = 1;
+    ga.M = (int32_t)n;
+    ga.N = 128;
+    ga.K = 64;
+    ga.kchunk = 64;
+    ga.C = buf<float>(ctx, B_SA);
+    ga.scm = 128;
+    ga.scn = 1;
+    hipLaunchKernelGGL(k_gemm, dim3(blocks_for(n, 128), 4, 1), dim3(256), 0, st, ga);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "surrogate preparation launch");
+  return ATM3_OK;
+}
+
+int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
+  if (G.np == 0) return ATM3_OK;
+  PairArgs pa;
+  pa.pij = buf<int2>(ctx, B_SP_IJ);
+  pa.prec = buf<float4>(ctx, B_SP_REC);
+  pa.A = buf<float>(ctx, B_SA);
+  pa.wp1 = m->wp1;
+  pa.wp2 = m->wp2;
+  pa.wp3 = m->wp3;
+  pa.P = m->params;
+  pa.np = (int32_t)G.np;
+  pa.rc = (float)G.rc;
+  pa.w = (float)((G.rc - R0) / (NR - 1));
+  pa.inv_w = (float)((NR - 1) / (G.rc - R0));
+  pa.st = buf<float2>(ctx, B_SP_ST);
+  pa.h1 = dump ? buf<bf16>(ctx, B_TH1) : nullptr;
+  pa.h2 = dump ? buf<bf16>(ctx, B_TH2) : nullptr;
+  pa.h3 = dump ? buf<bf16>(ctx, B_TH3) : nullptr;
+  pa.g16 = dump ? buf<bf16>(ctx, B_TG16) : nullptr;
+  int dev_cu = 256;
+  (void)hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  const int64_t tiles = (G.np + 31) / 32;
+  int64_t grid = 2 * (int64_t)dev_cu;
+  if (grid * 4 > tiles) grid = (tiles + 3) / 4;
+  hipLaunchKernelGGL(k_pair_mlp, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "pair MLP launch");
+  return ATM3_OK;
+}
+
+int sur_mol(atm3_ctx* ctx, const SurGeom& G, const atm3_params* p, float thr, bool with_lj, bool queue, float* forces,
+            float* err_out, bool keep_slot) {
+  int r;
+  const size_t N = (size_t)G.n;
+  const unsigned nb = blocks_for(G.n, 256);
+  if ((r = ensure(ctx, B_SRED, 16 * (size_t)nb + 64))) return r;
+  if ((r = ensure(ctx, B_SQ, 4 * (N + 1)))) return r;
+  if ((r = ensure(ctx, B_SF3, 16 * N))) return r;
+  if ((r = ensure(ctx, B_SE, 4 * N))) return r;
+  MolArgs ma;
+  ma.nb_start = buf<int32_t>(ctx, B_SN_START);
+  ma.nb = buf<int32_t>(ctx, B_SN_NB);
+  ma.prec = buf<float4>(ctx, B_SP_REC);
+  ma.st = buf<float2>(ctx, B_SP_ST);
+  ma.sorted = buf<double4>(ctx, B_SORTED);
+  ma.n = (int32_t)G.n;
+  ma.with_lj = with_lj ? 1 : 0;
+  ma.sig2 = p ? p->sigma * p->sigma : 1.0;
+  ma.eps24 = p ? 24.0 * p->eps : 0.0;
+  ma.thr = thr;
+  ma.forces = forces;
+  ma.err_out = err_out;
+  ma.f3s = keep_slot ? buf<float4>(ctx, B_SF3) : nullptr;
+  ma.es = keep_slot ? buf<float>(ctx, B_SE) : nullptr;
+  ma.queue = queue ? buf<int32_t>(ctx, B_SQ) : nullptr;
+  ma.red = buf<double>(ctx, B_SRED);
+  if (queue) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ma.queue, (int64_t)1);
+  hipLaunchKernelGGL(k_mol, dim3(nb), dim3(256), 0, ctx->stream, ma);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "force assembly launch");
+  return ATM3_OK;
+}
+
+// C[M][N] (+)= op products through k_gemm, split over K with a fixed-order sum.
+int gemm_splitk(atm3_ctx* ctx, GemmArgs ga, float* out) {
+  int r;
+  const int64_t MN = (int64_t)ga.M * ga.N;
+  int splits = (int)((ga.K + 4095) / 4096);
+  if (splits < 1) splits = 1;
+  if (splits > MAXSPLIT) splits = MAXSPLIT;
+  int64_t chunk = (ga.K + splits - 1) / splits;
+  chunk = (chunk + 15) / 16 * 16;
+  splits = (int)((ga.K + chunk - 1) / chunk);
+  if (splits < 1) splits = 1;
+  if ((r = ensure(ctx, B_TPART, 4 * (size_t)MN * splits))) return r;
+  ga.kchunk = (int32_t)chunk;
+  ga.C = buf<float>(ctx, B_TPART);
+  ga.scm = ga.N;
+  ga.scn = 1;
+  ga.scz = MN;
+  hipLaunchKernelGGL(k_gemm, dim3(blocks_for(ga.M, 128), blocks_for(ga.N, 32), splits), dim3(256), 0, ctx->stream,
+                     ga);
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(MN, 256)), dim3(256), 0, ctx->stream, buf<float>(ctx, B_TPART),
+                     splits, MN, MN, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "gemm launch");
+  return ATM3_OK;
+}
+
+int colsum(atm3_ctx* ctx, const float* X, int64_t rows, int cols, float* out) {
+  int r;
+  const int chunk = 4096;
+  const int parts = (int)((rows + chunk - 1) / chunk);
+  const int np = parts > 0 ? parts : 1;
+  if ((r = ensure(ctx, B_TPART, 4 * (size_t)cols * np))) return r;
+  if (rows > 0)
+    hipLaunchKernelGGL(k_colsum_part, dim3(parts), dim3(256), 0, ctx->stream, X, (int32_t)rows, cols, chunk,
+                       buf<float>(ctx, B_TPART));
+  else
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, ctx->stream, buf<float>(ctx, B_TPART), (int64_t)cols);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, ctx->stream, buf<float>(ctx, B_TPART), np, (int64_t)cols,
+                     (int64_t)cols, out);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "column sum launch");
+  return ATM3_OK;
+}
+
+int do_grad(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double* box, double rc,
+            const float* target, float lam, float* grad, double* loss_out) {
+  if (!target) return fail(ctx, ATM3_EINVAL, "f3_target is NULL");
+  SurGeom G;
+  int r = sur_prepare(ctx, m, pos, n, box, rc, false, &G);
+  if (r) return r;
+  const size_t P = (size_t)G.np, N = (size_t)n;
+  if ((r = ensure(ctx, B_TH1, 2 * 128 * P))) return r;
+  if ((r = ensure(ctx, B_TH2, 2 * 128 * P))) return r;
+  if ((r = ensure(ctx, B_TH3, 2 * 128 * P))) return r;
+  if ((r = ensure(ctx, B_TG16, 2 * 16 * P))) return r;
+  if ((r = sur_pairs_forward(ctx, m, G, true))) return r;
+  if ((r = sur_mol(ctx, G, nullptr, 0.f, false, false, nullptr, nullptr, true))) return r;
+  hipStream_t st = ctx->stream;
+  const unsigned nbk = blocks_for(n, 256);
+  if ((r = ensure(ctx, B_SG, 16 * N))) return r;
+  if ((r = ensure(ctx, B_SGE, 4 * N))) return r;
+  if ((r = ensure(ctx, B_SRED, 8 * (size_t)nbk + 64))) return r;
+  LossArgs la;
+  la.f3s = buf<float4>(ctx, B_SF3);
+  la.es = buf<float>(ctx, B_SE);
+  la.target = target;
+  la.sorted = buf<double4>(ctx, B_SORTED);
+  la.n = (int32_t)n;
+  la.lam = lam;
+  la.inv_n = (float)(1.0 / (double)n);
+  la.gF = buf<float4>(ctx, B_SG);
+  la.ge = buf<float>(ctx, B_SGE);
+  la.red = buf<double>(ctx, B_SRED);
+  hipLaunchKernelGGL(k_loss, dim3(nbk), dim3(256), 0, st, la);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, st, la.red, (int32_t)nbk, 1, m->dsum);
+  if (grad) {
+    if ((r = ensure(ctx, B_TDOUT, 8 * P + 8))) return r;
+    if ((r = ensure(ctx, B_TDOUTB, 4 * P + 4))) return r;
+    if ((r = ensure(ctx, B_TDZ3, 4 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDZ2, 4 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDZ1, 4 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDZ3B, 2 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDZ2B, 2 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDZ1B, 2 * 128 * P))) return r;
+    if ((r = ensure(ctx, B_TDA, 4 * 128 * N))) return r;
+    if ((r = ensure(ctx, B_TDAB, 2 * 128 * N))) return r;
+    const int64_t np = (int64_t)P;
+    if (np > 0) {
+      DoutArgs oa;
+      oa.pij = buf<int2>(ctx, B_SP_IJ);
+      oa.prec = buf<float4>(ctx, B_SP_REC);
+      oa.st = buf<float2>(ctx, B_SP_ST);
+      oa.gF = la.gF;
+      oa.ge = la.ge;
+      oa.h3 = buf<bf16>(ctx, B_TH3);
+      oa.P = m->params;
+      oa.np = (int32_t)np;
+      oa.dout = buf<float>(ctx, B_TDOUT);
+      oa.doutb = buf<bf16>(ctx, B_TDOUTB);
+      oa.dz3 = buf<float>(ctx, B_TDZ3);
+      oa.dz3b = buf<bf16>(ctx, B_TDZ3B);
+      hipLaunchKernelGGL(k_dout, dim3(blocks_for(32 * np, 256)), dim3(256), 0, st, oa);
+      // dz2 = (dz3 W3^T) * (h2 > 0); dz1 = (dz2 W2^T) * (h1 > 0)
+      for (int layer = 0; layer < 2; ++layer) {
+        GemmArgs ga = {};
+        ga.A = layer == 0 ? buf<bf16>(ctx, B_TDZ3B) : buf<bf16>(ctx, B_TDZ2B);
+        ga.sam = 128;
+        ga.sak = 1;
+        ga.B = layer == 0 ? m->w3b : m->w2b;  // B(k, n) = W[n][k]
+        ga.sbk = 1;
+        ga.sbn = 128;
+        ga.M = (int32_t)np;
+        ga.N = 128;
+        ga.K = 128;
+        ga.kchunk = 128;
+        ga.C = layer == 0 ? buf<float>(ctx, B_TDZ2) : buf<float>(ctx, B_TDZ1);
+        ga.scm = 128;
+        ga.scn = 1;
+        ga.Cb = layer == 0 ? buf<bf16>(ctx, B_TDZ2B) : buf<bf16>(ctx, B_TDZ1B);
+        ga.sbm2 = 128;
+        ga.sbn2 = 1;
+        ga.mask = layer == 0 ? buf<bf16>(ctx, B_TH2) : buf<bf16>(ctx, B_TH1);
+        ga.smm = 128;
+        ga.smn = 1;
+        hipLaunchKernelGGL(k_gemm, dim3(blocks_for(np, 128), 4, 1), dim3(256), 0, st, ga);
+      }
+    }
+    // weight gradients (split-K over pairs), bias gradients (column sums)
+    struct WG {
+      Buf x;
+      int xcols;
+      Buf y;
+      int ycols;
+      int off;
+    };
+    const WG wg[4] = {{B_TH3, 128, B_TDOUTB, 2, OFF_W4},
+                      {B_TH2, 128, B_TDZ3B, 128, OFF_W3},
+                      {B_TH1, 128, B_TDZ2B, 128, OFF_W2},
+                      {B_TG16, 16, B_TDZ1B, 128, OFF_W1 + NDESC * WID}};
+    for (const WG& w : wg) {
+      GemmArgs ga = {};
+      ga.A = buf<bf16>(ctx, w.x);  // A(m, k) = X[k][m]
+      ga.sam = 1;
+      ga.sak = w.xcols;
+      ga.B = buf<bf16>(ctx, w.y);  // B(k, n) = Y[k][n]
+      ga.sbk = w.ycols;
+      ga.sbn = 1;
+      ga.M = w.xcols;
+      ga.N = w.ycols;
+      ga.K = (int32_t)np;
+      if ((r = gemm_splitk(ctx, ga, grad + w.off))) return r;
+    }
+    if ((r = colsum(ctx, buf<float>(ctx, B_TDOUT), np, 2, grad + OFF_B4))) return r;
+    if ((r = colsum(ctx, buf<float>(ctx, B_TDZ3), np, 128, grad + OFF_B3))) return r;
+    if ((r = colsum(ctx, buf<float>(ctx, B_TDZ2), np, 128, grad + OFF_B2))) return r;
+    if ((r = colsum(ctx, buf<float>(ctx, B_TDZ1), np, 128, grad + OFF_B1))) return r;
+    // dA per slot, then dW1a = D^T dA (split-K over molecules)
+    hipLaunchKernelGGL(k_dA, dim3(blocks_for(32 * (int64_t)n, 256)), dim3(256), 0, st, buf<int32_t>(ctx, B_SN_START),
+                       buf<int32_t>(ctx, B_SN_NB), buf<float>(ctx, B_TDZ1), (int32_t)n, buf<float>(ctx, B_TDA),
+                       buf<bf16>(ctx, B_TDAB));
+    GemmArgs ga = {};
+    ga.A = buf<bf16>(ctx, B_SDB);
+    ga.sam = 1;
+    ga.sak = 64;
+    ga.B = buf<bf16>(ctx, B_TDAB);
+    ga.sbk = 128;
+    ga.sbn = 1;
+    ga.M = 64;
+    ga.N = 128;
+    ga.K = (int32_t)n;
+    if ((r = gemm_splitk(ctx, ga, grad + OFF_W1))) return r;
+  }
+  double loss = 0.0;
+  hipError_t e = hipMemcpyAsync(&loss, m->dsum, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "loss copy");
+  if (loss_out) *loss_out = loss / (double)n;
+  return ATM3_OK;
+}
+
+int do_adam(atm3_ctx* ctx, atm3_mlp* m, const float* grad, float lr, float b1, float b2, float eps) {
+  if (!grad) return fail(ctx, ATM3_EINVAL, "grad is NULL");
+  if (!(lr >= 0.f) || !(b1 >= 0.f && b1 < 1.f) || !(b2 >= 0.f && b2 < 1.f) || !(eps > 0.f))
+    return fail(ctx, ATM3_EINVAL, "invalid Adam hyper-parameters");
+  m->step += 1;
+  const float c1 = (float)(1.0 - pow((double)b1, (double)m->step));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)m->step));
+  hipLaunchKernelGGL(k_adam, dim3(blocks_for(NPARAM, 256)), dim3(256), 0, ctx->stream, m->params, m->m, m->v, grad,
+                     NPARAM, lr, b1, b2, eps, c1, c2);
+  hipError_t e = prep_weights(ctx, m);
+  if (e != hipSuccess) return hip_fail(ctx, e, "Adam launch");
+  return ATM3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int atm3_mlp_create(atm3_ctx* ctx, uint64_t seed, atm3_mlp** out) {
+  if (!ctx || !out) return ATM3_EINVAL;
+  ctx->err.clear();
+  *out = nullptr;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice");
+  atm3_mlp* m = new (std::nothrow) atm3_mlp();
+  if (!m) return fail(ctx, ATM3_ENOMEM, "host allocation");
+  m->device = ctx->device;
+  bool ok = hipMalloc(&m->params, 4 * NPARAM) == hipSuccess && hipMalloc(&m->m, 4 * NPARAM) == hipSuccess &&
+            hipMalloc(&m->v, 4 * NPARAM) == hipSuccess && hipMalloc(&m->grad, 4 * NPARAM) == hipSuccess &&
+            hipMalloc(&m->stats, 4 * 128) == hipSuccess && hipMalloc(&m->w1b, 2 * NIN * WID) == hipSuccess &&
+            hipMalloc(&m->w2b, 2 * WID * WID) == hipSuccess && hipMalloc(&m->w3b, 2 * WID * WID) == hipSuccess &&
+            hipMalloc(&m->wp1, 2 * NPERM1) == hipSuccess && hipMalloc(&m->wp2, 2 * NPERM) == hipSuccess &&
+            hipMalloc(&m->wp3, 2 * NPERM) == hipSuccess && hipMalloc(&m->dsum, 64) == hipSuccess;
+  if (!ok) {
+    atm3_mlp_destroy(m);
+    return fail(ctx, ATM3_ENOMEM, "device allocation for the model");
+  }
+  std::vector<float> h(NPARAM, 0.f);
+  uint64_t s = seed;
+  for (int i = 0; i < NIN * WID; ++i) h[OFF_W1 + i] = (float)(normal(&s) * sqrt(2.0 / NIN));
+  for (int i = 0; i < WID * WID; ++i) h[OFF_W2 + i] = (float)(normal(&s) * sqrt(2.0 / WID));
+  for (int i = 0; i < WID * WID; ++i) h[OFF_W3 + i] = (float)(normal(&s) * sqrt(2.0 / WID));
+  for (int i = 0; i < 2 * WID; ++i) h[OFF_W4 + i] = (float)(0.1 * normal(&s) * sqrt(1.0 / WID));
+  h[OFF_B4 + 1] = -3.f;
+  std::vector<float> st(128, 0.f);
+  for (int i = 64; i < 128; ++i) st[i] = 1.f;
+  e = hipMemcpy(m->params, h.data(), 4 * NPARAM, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->stats, st.data(), 4 * 128, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->m, 0, 4 * NPARAM);
+  if (e == hipSuccess) e = hipMemset(m->v, 0, 4 * NPARAM);
+  if (e == hipSuccess) e = prep_weights(ctx, m);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    atm3_mlp_destroy(m);
+    return hip_fail(ctx, e, "model initialisation");
+  }
+  *out = m;
+  return ATM3_OK;
+}
+
+void atm3_mlp_destroy(atm3_mlp* m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  void* ps[] = {m->params, m->m, m->v, m->grad, m->stats, m->w1b, m->w2b, m->w3b, m->wp1, m->wp2, m->wp3, m->dsum};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+int atm3_mlp_set_params(atm3_ctx* ctx, atm3_mlp* m, const float* host, int64_t n) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!host || n != NPARAM) return fail(ctx, ATM3_EINVAL, "parameter count must be ATM3_MLP_NPARAM");
+  hipError_t e = hipMemcpy(m->params, host, 4 * NPARAM, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->m, 0, 4 * NPARAM);
+  if (e == hipSuccess) e = hipMemset(m->v, 0, 4 * NPARAM);
+  if (e == hipSuccess) e = prep_weights(ctx, m);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "set params");
+  m->step = 0;
+  return ATM3_OK;
+}
+
+int atm3_mlp_get_params(atm3_ctx* ctx, atm3_mlp* m, float* host, int64_t n) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!host || n != NPARAM) return fail(ctx, ATM3_EINVAL, "parameter count must be ATM3_MLP_NPARAM");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(host, m->params, 4 * NPARAM, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "get params");
+  return ATM3_OK;
+}
+
+int atm3_mlp_set_stats(atm3_ctx* ctx, atm3_mlp* m, const float* mean, const float* inv_sd) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!mean || !inv_sd) return fail(ctx, ATM3_EINVAL, "NULL statistics");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(m->stats, mean, 4 * 64, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(m->stats + 64, inv_sd, 4 * 64, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "set stats");
+  return ATM3_OK;
+}
+
+int atm3_mlp_get_stats(atm3_ctx* ctx, atm3_mlp* m, float* mean, float* inv_sd) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!mean || !inv_sd) return fail(ctx, ATM3_EINVAL, "NULL statistics");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(mean, m->stats, 4 * 64, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(inv_sd, m->stats + 64, 4 * 64, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "get stats");
+  return ATM3_OK;
+}
+
+int atm3_mlp_fit_stats(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double box[3], double rc) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  SurGeom G;
+  if ((r = sur_prepare(ctx, m, pos, n, box, rc, true, &G))) return r;
+  const int chunk = 2048;
+  const int parts = (int)((n + chunk - 1) / chunk);
+  if ((r = ensure(ctx, B_SRED, 8 * 128 * (size_t)parts))) return r;
+  hipLaunchKernelGGL(k_colstats_part, dim3(parts), dim3(256), 0, ctx->stream, buf<float>(ctx, B_SD), (int32_t)n,
+                     chunk, buf<double>(ctx, B_SRED));
+  hipLaunchKernelGGL(k_colstats_final, dim3(1), dim3(64), 0, ctx->stream, buf<double>(ctx, B_SRED), parts,
+                     (int32_t)n, m->stats);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "fit stats");
+  return ATM3_OK;
+}
+
+int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double box[3],
+                          const atm3_params* p, float thr, float* forces, float* err_est, atm3_result* out,
+                          int64_t* n_fallback) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!p || !forces || !out) return fail(ctx, ATM3_EINVAL, "params, forces or result is NULL");
+  if (!(p->sigma > 0.0) || !isfinite(p->eps) || !isfinite(p->nu))
+    return fail(ctx, ATM3_EINVAL, "sigma must be > 0, eps and nu finite");
+  if (p->truncation != ATM3_TRUNC_PAIR) return fail(ctx, ATM3_EINVAL, "the surrogate uses the pairwise cutoff");
+  SurGeom G;
+  if ((r = sur_prepare(ctx, m, pos, n, box, p->rc, false, &G))) return r;
+  if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
+  if ((r = sur_mol(ctx, G, p, thr, true, true, forces, err_est, false))) return r;
+  hipStream_t st = ctx->stream;
+  const unsigned nbk = blocks_for(n, 256);
+  unsigned long long* ntrip = (unsigned long long*)(m->dsum + 4);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t*)ntrip, (int64_t)2);
+  FallArgs fa;
+  fa.queue = buf<int32_t>(ctx, B_SQ);
+  fa.nb_start = buf<int32_t>(ctx, B_SN_START);
+  fa.nb = buf<int32_t>(ctx, B_SN_NB);
+  fa.pij = buf<int2>(ctx, B_SP_IJ);
+  fa.prec = buf<float4>(ctx, B_SP_REC);
+  fa.sorted = buf<double4>(ctx, B_SORTED);
+  fa.pos = pos;
+  for (int d = 0; d < 3; ++d) fa.box[d] = box[d];
+  fa.rc2 = p->rc * p->rc;
+  fa.lo2 = (float)(fa.rc2 * (1.0 - 4e-5));
+  fa.hi2 = (float)(fa.rc2 * (1.0 + 4e-5));
+  fa.k3nu = (float)(3.0 * p->nu);
+  fa.k15nu = (float)(1.875 * p->nu);
+  fa.k075nu = (float)(0.75 * p->nu);
+  fa.forces = forces;
+  fa.ntrip = ntrip;
+  int dev_cu = 256;
+  (void)hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
+  hipLaunchKernelGGL(k_fallback, dim3(8 * dev_cu), dim3(256), 0, st, fa);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, st, buf<double>(ctx, B_SRED), (int32_t)nbk, 2, m->dsum);
+  hipError_t e = hipGetLastError();
+  double sums[2];
+  unsigned long long nt = 0;
+  int32_t nq = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(sums, m->dsum, 16, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nt, ntrip, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&nq, buf<int32_t>(ctx, B_SQ), 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "surrogate evaluation");
+  atm3_result res = {};
+  res.e_lj = 4.0 * p->eps * sums[0];
+  res.w_lj = 24.0 * p->eps * sums[1];
+  res.e_atm = NAN;
+  res.w_atm = NAN;
+  res.n_pairs = G.np;
+  res.n_triplets = (int64_t)nt;
+  res.n_candidates = 0;
+  for (int d = 0; d < 3; ++d) res.ncell[d] = G.g.n[d];
+  res.status = ATM3_OK;
+  *out = res;
+  if (n_fallback) *n_fallback = nq;
+  return ATM3_OK;
+}
+
+int atm3_mlp_grad(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double box[3], double rc,
+                  const float* f3_target, float lam, float* grad_dev, double* loss_out) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!(lam >= 0.f)) return fail(ctx, ATM3_EINVAL, "lam must be >= 0");
+  return do_grad(ctx, m, pos, n, box, rc, f3_target, lam, grad_dev, loss_out);
+}
+
+int atm3_mlp_adam(atm3_ctx* ctx, atm3_mlp* m, const float* grad_dev, float lr, float beta1, float beta2, float eps) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  return do_adam(ctx, m, grad_dev, lr, beta1, beta2, eps);
+}
+
+int atm3_mlp_train_step(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double box[3], double rc,
+                        const float* f3_target, float lam, float lr, double* loss_out) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (!(lam >= 0.f)) return fail(ctx, ATM3_EINVAL, "lam must be >= 0");
+  if ((r = do_grad(ctx, m, pos, n, box, rc, f3_target, lam, m->grad, loss_out))) return r;
+  return do_adam(ctx, m, m->grad, lr, 0.9f, 0.999f, 1e-8f);
+}
+
+int atm3_surrogate_pairs(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double box[3], double rc,
+                         int64_t cap, int32_t* pair_ij, float* st_out, float* desc, float* f3, float* err,
+                         int64_t* n_pairs) {
+  int r = begin(ctx, m);
+  if (r) return r;
+  if (cap < 0) return fail(ctx, ATM3_EINVAL, "cap must be >= 0");
+  SurGeom G;
+  if ((r = sur_prepare(ctx, m, pos, n, box, rc, false, &G))) return r;
+  if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
+  if ((r = sur_mol(ctx, G, nullptr, 0.f, false, false, nullptr, err, true))) return r;
+  hipStream_t st = ctx->stream;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(ctx, e, "surrogate evaluation");
+  // gather to input order on the host side of the boundary: small copies
+  const int64_t np = G.np < cap ? G.np : cap;
+  std::vector<int32_t> perm(n);
+  e = hipMemcpy(perm.data(), buf<int32_t>(ctx, B_PERM), 4 * (size_t)n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+  if (pair_ij && np > 0) {
+    std::vector<int2> ij(np);
+    e = hipMemcpy(ij.data(), buf<int2>(ctx, B_SP_IJ), 8 * (size_t)np, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+    std::vector<int32_t> o(2 * np);
+    for (int64_t q = 0; q < np; ++q) {
+      o[2 * q] = perm[ij[q].x];
+      o[2 * q + 1] = perm[ij[q].y];
+    }
+    e = hipMemcpy(pair_ij, o.data(), 8 * (size_t)np, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+  }
+  if (st_out && np > 0) {
+    e = hipMemcpy(st_out, buf<float2>(ctx, B_SP_ST), 8 * (size_t)np, hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+  }
+  if (desc || f3) {
+    std::vector<float> d(64 * (size_t)n), o(64 * (size_t)n);
+    std::vector<float4> f(n);
+    if (desc) {
+      e = hipMemcpy(d.data(), buf<float>(ctx, B_SD), 4 * 64 * (size_t)n, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+      for (int64_t s = 0; s < n; ++s)
+        for (int c = 0; c < 64; ++c) o[64 * (size_t)perm[s] + c] = d[64 * (size_t)s + c];
+      e = hipMemcpy(desc, o.data(), 4 * 64 * (size_t)n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+    }
+    if (f3) {
+      e = hipMemcpy(f.data(), buf<float4>(ctx, B_SF3), 16 * (size_t)n, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+      std::vector<float> g3(3 * (size_t)n);
+      for (int64_t s = 0; s < n; ++s) {
+        g3[3 * (size_t)perm[s] + 0] = f[s].x;
+        g3[3 * (size_t)perm[s] + 1] = f[s].y;
+        g3[3 * (size_t)perm[s] + 2] = f[s].z;
+      }
+      e = hipMemcpy(f3, g3.data(), 12 * (size_t)n, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "copy");
+    }
+  }
+  if (n_pairs) *n_pairs = G.np;
+  return ATM3_OK;
+}
+
+}  // extern "C"

@@ -53,3 +53,12 @@ def test_null_context_is_einval():
     box = (ctypes.c_double * 3)(10.0, 10.0, 10.0)
     nc = (ctypes.c_int32 * 3)()
     assert lib.atm3_bin_cells(None, None, 0, box, 2.5, None, None, None, nc) == _lib.ATM3_EINVAL
+
+
+def test_null_model_is_einval():
+    from paper_2510_21230_amd import _lib
+    lib = _lib.load()
+    assert lib.atm3_mlp_create(None, 0, None) == _lib.ATM3_EINVAL
+    assert lib.atm3_mlp_get_params(None, None, None, 0) == _lib.ATM3_EINVAL
+    assert lib.atm3_mlp_train_step(None, None, None, 0, None, 2.5, None, 1.0, 1e-3, None) == _lib.ATM3_EINVAL
+    lib.atm3_mlp_destroy(None)
