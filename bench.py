@@ -89,6 +89,65 @@ def cpu_baseline(pos, box, params, budget_s=15.0):
                       f"on each by the per-molecule FP64 oracle (OpenMP), {dt:.1f} s"}
 
 
+def surrogate_leg(pos, box, f_exact, params, args):
+    """Train the learned pair surrogate on the GPU on exact ATM forces that
+    the exact kernel generates for the two smaller workloads: the N=1,000
+    jittered FCC at density 0.6, and frames every 10 steps of a 100-step
+    velocity-Verlet run of N=32,000 (FCC 20^3, density 0.7, Maxwell T=1.0,
+    dt=0.002).  Then time it on the benchmark system and measure its force
+    error against the exact LJ + ATM forces computed above."""
+    import torch
+
+    import paper_2510_21230_amd as atm3
+    from paper_2510_21230_amd import workloads
+
+    dev = pos.device
+    frames = []
+    p1, b1 = workloads.make("fcc1k")
+    p1 = torch.from_numpy(p1).to(dev)
+    frames.append((p1, b1, atm3.compute_forces(p1, b1, nu=params["nu"], terms=atm3.TERM_ATM)[0]))
+    p2, b2 = workloads.fcc(32000, 0.7, jitter=0.0, seed=workloads.SEED_BASE + 2)
+    v2 = torch.from_numpy(workloads.maxwell(32000, 1.0, seed=workloads.SEED_BASE + 3)).to(dev)
+    p2 = torch.from_numpy(p2).to(dev)
+    traj = []
+    atm3.md_run(p2, v2, b2, 100, dt=0.002, record_every=10, frames=traj, **params)
+    for fpos, _ in traj[1:]:
+        frames.append((fpos, b2, atm3.compute_forces(fpos, b2, nu=params["nu"], terms=atm3.TERM_ATM)[0]))
+    mlp = atm3.Mlp(seed=3)
+    mlp.fit_stats(frames[-1][0], frames[-1][1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(args.surrogate_train_steps):
+        fpos, fb, f3 = frames[it % len(frames)]
+        lr = 2e-3 if it < args.surrogate_train_steps * 0.7 else 5e-4
+        losses.append(mlp.train_step(fpos, fb, f3, lam=1.0, lr=lr))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    n = pos.shape[0]
+    f_lj, _ = atm3.compute_forces(pos, box, terms=atm3.TERM_LJ, **params)
+    rms = lambda a: float(torch.sqrt(torch.mean(torch.sum((a.double() - f_exact.double()) ** 2, dim=1))))
+    e_lj = rms(f_lj)
+    out = {"train_steps": args.surrogate_train_steps, "train_seconds": t_train, "train_frames": len(frames),
+           "train_loss_first": losses[0], "train_loss_last": float(sum(losses[-20:]) / min(20, len(losses))),
+           "force_rms_error_lj_only": e_lj, "force_rms_exact": rms(torch.zeros_like(f_exact))}
+    for tag, thr in (("fallback_1e-3", 1e-3), ("no_fallback", float("inf"))):
+        f_s = torch.empty_like(f_exact)
+        mlp.forces(pos, box, threshold=thr, forces=f_s, **params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.surrogate_steps):
+            _, r, nf, _ = mlp.forces(pos, box, threshold=thr, forces=f_s, **params)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.surrogate_steps
+        out[tag] = {"value": n / dt, "unit": "molecule updates/s", "ms_per_step": dt * 1e3,
+                    "threshold": thr if thr != float("inf") else None,
+                    "fallback_fraction": nf / n, "force_rms_error": rms(f_s),
+                    "gain_vs_lj_only": e_lj / max(rms(f_s), 1e-30)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +156,9 @@ def main():
     ap.add_argument("--workload", default="fcc1m", choices=["fcc1m", "fcc32k", "fcc1k", "slab20k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--surrogate-train-steps", type=int, default=600,
+                    help="training steps of the surrogate before its timing (0: skip the surrogate leg)")
+    ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -183,9 +245,11 @@ def main():
                    "hit_rate": r["n_triplets"] / max(r["n_candidates"], 1)},
         "energies": {"e_lj": r["e_lj"], "e_atm": r["e_atm"], "w_lj": r["w_lj"], "w_atm": r["w_atm"]},
     }
+    if args.surrogate_train_steps > 0:
+        out["surrogate"] = surrogate_leg(pos, box, forces, params, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pos_np, box, params, budget_s=args.cpu_budget)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

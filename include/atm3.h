@@ -263,6 +263,20 @@ int atm3_surrogate_pairs(atm3_ctx* ctx, atm3_mlp* mlp, const double* pos, int64_
                          double rc, int64_t cap, int32_t* pair_ij, float* st, float* desc, float* f3, float* err,
                          int64_t* n_pairs);
 
+/* ------------------------------------------------------------------------
+ * Molecular dynamics driver: velocity Verlet (NVE), unit mass, reduced LJ
+ * units, FP64 positions and velocities (device, n*3, molecule-major), FP32
+ * forces (device, n*3, e.g. from atm3_compute_forces).  One step is
+ *   atm3_md_kick_drift(dt)   v += dt/2 F(x);  x += dt v
+ *   (new forces F(x))
+ *   atm3_md_kick(dt)         v += dt/2 F(x)
+ * Positions are not wrapped (the force routines accept any image).  Both
+ * only enqueue.  atm3_md_kinetic returns sum v^2 / 2 (FP64, fixed-order
+ * reduction) and blocks. */
+int atm3_md_kick_drift(atm3_ctx* ctx, double* pos, double* vel, const float* forces, int64_t n, double dt);
+int atm3_md_kick(atm3_ctx* ctx, double* vel, const float* forces, int64_t n, double dt);
+int atm3_md_kinetic(atm3_ctx* ctx, const double* vel, int64_t n, double* ke_out);
+
 #ifdef __cplusplus
 }
 #endif

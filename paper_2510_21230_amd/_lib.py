@@ -33,6 +33,7 @@ EXPORTS = (
     "atm3_mlp_create", "atm3_mlp_destroy", "atm3_mlp_set_params", "atm3_mlp_get_params",
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
+    "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic",
 )
 MLP_NPARAM = 43650
 MLP_NDESC = 64
@@ -129,6 +130,12 @@ def load():
         lib.atm3_surrogate_pairs.argtypes = [vp, vp, vp, i64, dptr, ctypes.c_double, i64, vp, vp, vp, vp, vp,
                                              ctypes.POINTER(i64)]
         lib.atm3_surrogate_pairs.restype = ctypes.c_int
+        lib.atm3_md_kick_drift.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double]
+        lib.atm3_md_kick_drift.restype = ctypes.c_int
+        lib.atm3_md_kick.argtypes = [vp, vp, vp, i64, ctypes.c_double]
+        lib.atm3_md_kick.restype = ctypes.c_int
+        lib.atm3_md_kinetic.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_double)]
+        lib.atm3_md_kinetic.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -420,3 +427,39 @@ class Mlp:
                                                       _ptr(ij), _ptr(st), _ptr(desc), _ptr(f3), _ptr(err),
                                                       ctypes.byref(npairs)))
         return {"pair_ij": ij[:P], "st": st[:P], "desc": desc, "f3": f3, "err": err, "n_pairs": npairs.value}
+
+
+def md_run(pos, vel, box, steps, dt=0.002, record_every=1, frames=None, **force_kw):
+    """Velocity Verlet (NVE) for `steps` steps, updating the FP64 device
+    tensors `pos` and `vel` in place, with forces from atm3_compute_forces.
+    Returns the per-recorded-step dicts (step, kinetic, e_lj, e_atm, total);
+    if `frames` is a list, copies of (pos, forces) at the recorded steps are
+    appended to it."""
+    import torch
+    ctx = context(pos.device)
+    lib = ctx.lib
+    if not (vel.is_cuda and vel.dtype == torch.float64 and vel.shape == pos.shape and vel.is_contiguous()):
+        raise ValueError("vel must be a contiguous float64 tensor shaped like pos")
+    if not pos.is_contiguous():
+        raise ValueError("pos must be contiguous")
+    n = pos.shape[0]
+    f, r = ctx.compute_forces(pos, box, **force_kw)
+    out = []
+
+    def record(k, res):
+        ke = ctypes.c_double()
+        ctx._check(lib.atm3_md_kinetic(ctx.h, _ptr(vel), n, ctypes.byref(ke)))
+        out.append({"step": k, "kinetic": ke.value, "e_lj": res["e_lj"], "e_atm": res["e_atm"],
+                    "total": ke.value + res["e_lj"] + res["e_atm"]})
+        if frames is not None:
+            frames.append((pos.clone(), f.clone()))
+
+    record(0, r)
+    for k in range(1, steps + 1):
+        ctx._stream()
+        ctx._check(lib.atm3_md_kick_drift(ctx.h, _ptr(pos), _ptr(vel), _ptr(f), n, float(dt)))
+        f, r = ctx.compute_forces(pos, box, forces=f, **force_kw)
+        ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
+        if k % record_every == 0:
+            record(k, r)
+    return out

@@ -21,6 +21,7 @@ SOURCES = {
     "atm3_binning.hip": ["-ffp-contract=off"],
     "atm3_forces.hip": [],
     "atm3_surrogate.hip": [],
+    "atm3_md.hip": [],
 }
 
 COMMON = [

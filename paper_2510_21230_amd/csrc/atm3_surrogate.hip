@@ -49,7 +49,7 @@ __device__ __forceinline__ f32x16 mfma32(const bf16x8 a, const bf16x8 b, const f
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float softplusf(float t) { return fmaxf(t, 0.f) + log1pf(expf(-fabsf(t))); }
+__device__ __forceinline__ float softplusf(float t) { return fmaxf(t, 0.f) + __logf(1.f + __expf(-fabsf(t))); }
 
 // --------------------------------------------------------------------------
 // neighbour lists
@@ -71,55 +71,60 @@ struct NbArgs {
   float4* prec;
 };
 
-// Visit the neighbours t != s of slot s (r_st^2 < rc^2) in the fixed order of
-// the 27 cells and the slots within a cell.  The distance comes from the
-// cell-centred FP64 records; inside a 1e-9 relative band around rc^2 the
-// decision is the exact minimum-image expression on the input positions.
+// Visit the neighbours t of slot s that s lists as the pair's first member:
+// the molecules of its own cell with a larger slot and all molecules of the
+// 13 forward neighbour cells (offsets after (0,0,0) in z, y, x order), so
+// that every pair is found exactly once; fixed order of cells and of slots
+// within a cell.  The distance comes from the cell-centred FP64 records;
+// inside a 1e-9 relative band around rc^2 the decision is the exact
+// minimum-image expression on the input positions.
 template <class F>
-__device__ __forceinline__ void for_neighbours(const NbArgs& a, int s, F&& f) {
+__device__ __forceinline__ void for_half_shell(const NbArgs& a, int s, F&& f) {
   const double4 me = a.sorted[s];
   const int orig = (int)me.w;
   const int c = a.cell_of[orig];
   const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
-  for (int dz = -1; dz <= 1; ++dz) {
+  for (int q = 13; q < 27; ++q) {
+    const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
     int uz = cz + dz;
     uz = uz < 0 ? uz + a.nz : (uz >= a.nz ? uz - a.nz : uz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      int uy = cy + dy;
-      uy = uy < 0 ? uy + a.ny : (uy >= a.ny ? uy - a.ny : uy);
-      for (int dx = -1; dx <= 1; ++dx) {
-        int ux = cx + dx;
-        ux = ux < 0 ? ux + a.nx : (ux >= a.nx ? ux - a.nx : ux);
-        const int cc = (uz * a.ny + uy) * a.nx + ux;
-        const double ox = dx * a.side[0], oy = dy * a.side[1], oz = dz * a.side[2];
-        const int t1 = a.start[cc + 1];
-        for (int t = a.start[cc]; t < t1; ++t) {
-          if (t == s) continue;
-          const double4 o = a.sorted[t];
-          // r_s - r_t = loc_s - loc_t - offset of t's cell
-          const double ex = (me.x - o.x) - ox, ey = (me.y - o.y) - oy, ez = (me.z - o.z) - oz;
-          const double r2 = ex * ex + ey * ey + ez * ez;
-          bool in;
-          if (r2 < a.lo2) in = true;
-          else if (r2 >= a.hi2) in = false;
-          else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
-          if (in) f(t, ex, ey, ez, r2);
-        }
-      }
+    int uy = cy + dy;
+    uy = uy < 0 ? uy + a.ny : (uy >= a.ny ? uy - a.ny : uy);
+    int ux = cx + dx;
+    ux = ux < 0 ? ux + a.nx : (ux >= a.nx ? ux - a.nx : ux);
+    const int cc = (uz * a.ny + uy) * a.nx + ux;
+    const double ox = dx * a.side[0], oy = dy * a.side[1], oz = dz * a.side[2];
+    const int t1 = a.start[cc + 1];
+    for (int t = (q == 13) ? s + 1 : a.start[cc]; t < t1; ++t) {
+      const double4 o = a.sorted[t];
+      // r_s - r_t = loc_s - loc_t - offset of t's cell
+      const double ex = (me.x - o.x) - ox, ey = (me.y - o.y) - oy, ez = (me.z - o.z) - oz;
+      const double r2 = ex * ex + ey * ey + ez * ez;
+      bool in;
+      if (r2 < a.lo2) in = true;
+      else if (r2 >= a.hi2) in = false;
+      else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
+      if (in) f(t, ex, ey, ez, r2);
     }
   }
 }
 
+// Pairs listed first by each slot; every pair also counts for its second slot.
 __global__ __launch_bounds__(256) void k_nb_count(NbArgs a) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n) return;
-  int all = 0, up = 0;
-  for_neighbours(a, s, [&](int t, double, double, double, double) {
-    ++all;
-    up += (t > s);
+  int up = 0;
+  for_half_shell(a, s, [&](int t, double, double, double, double) {
+    ++up;
+    atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
   });
-  a.n_all[s] = all;
   a.n_up[s] = up;
+}
+
+__global__ __launch_bounds__(256) void k_nb_total(const int32_t* __restrict__ n_up, int32_t n,
+                                                  int32_t* __restrict__ n_all) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n) n_all[s] += n_up[s];
 }
 
 __global__ __launch_bounds__(256) void k_nb_fill(NbArgs a) {
@@ -127,14 +132,12 @@ __global__ __launch_bounds__(256) void k_nb_fill(NbArgs a) {
   if (s >= a.n) return;
   int k = 0;
   const int p0 = a.up_start[s], e0 = a.nb_start[s];
-  for_neighbours(a, s, [&](int t, double ex, double ey, double ez, double r2) {
-    if (t > s) {
-      const int pid = p0 + k;
-      a.pij[pid] = make_int2(s, t);
-      a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
-      a.nb[e0 + k] = 2 * pid;
-      ++k;
-    }
+  for_half_shell(a, s, [&](int t, double ex, double ey, double ez, double r2) {
+    const int pid = p0 + k;
+    a.pij[pid] = make_int2(s, t);
+    a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
+    a.nb[e0 + k] = 2 * pid;
+    ++k;
   });
 }
 
@@ -150,12 +153,33 @@ __global__ __launch_bounds__(256) void k_nb_lower(const int2* __restrict__ pij, 
   nb[slot] = 2 * pid + 1;
 }
 
+// Sort each slot's second-member entries by pair number: in LDS when they
+// fit (SORT_CAP per thread, odd stride against bank conflicts), else in place.
+constexpr int SORT_CAP = 48, SORT_STRIDE = 49;
+
 __global__ __launch_bounds__(256) void k_nb_sort(const int32_t* __restrict__ nb_start,
                                                  const int32_t* __restrict__ n_up, int32_t n,
                                                  int32_t* __restrict__ nb) {
+  __shared__ int32_t lds[256 * SORT_STRIDE];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int lo = nb_start[s] + n_up[s], hi = nb_start[s + 1];
+  const int len = hi - lo;
+  if (len <= SORT_CAP) {
+    int32_t* b = lds + threadIdx.x * SORT_STRIDE;
+    for (int x = 0; x < len; ++x) b[x] = nb[lo + x];
+    for (int x = 1; x < len; ++x) {
+      const int v = b[x];
+      int y = x - 1;
+      while (y >= 0 && b[y] > v) {
+        b[y + 1] = b[y];
+        --y;
+      }
+      b[y + 1] = v;
+    }
+    for (int x = 0; x < len; ++x) nb[lo + x] = b[x];
+    return;
+  }
   for (int x = lo + 1; x < hi; ++x) {
     const int v = nb[x];
     int y = x - 1;
@@ -210,12 +234,12 @@ __global__ __launch_bounds__(256) void k_desc(DescArgs a) {
     const float sg = (v & 1) ? 1.f : -1.f;
     const float ir = 1.f / d.w;
     const float ux = sg * d.x * ir, uy = sg * d.y * ir, uz = sg * d.z * ir;
-    const float fc = 0.5f * (1.f + cosf(PI_F * d.w / a.rc));
+    const float fc = 0.5f * (1.f + __cosf(PI_F * d.w / a.rc));
     const float third = 1.f / 3.f;
     for (int c = 0; c < 4; ++c) {
       const int ch = 4 * cg + c;
       const float q = (d.w - (R0 + ch * a.w)) * a.inv_w;
-      const float g = expf(-q * q) * fc;
+      const float g = __expf(-q * q) * fc;
       S[c] += g;
       V[c][0] += g * ux;
       V[c][1] += g * uy;
@@ -420,7 +444,8 @@ __device__ __forceinline__ void dump4(bf16* dst, const f32x16& v, int base_reg) 
   *(bf16x4*)dst = t;
 }
 
-__global__ __launch_bounds__(256) void k_pair_mlp(PairArgs a) {
+template <bool DUMP>
+__global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
   __shared__ bf16x8 w1s[4 * 64];
   __shared__ bf16x8 w2s[32 * 64];
   __shared__ bf16x8 w3s[32 * 64];
@@ -459,14 +484,14 @@ __global__ __launch_bounds__(256) void k_pair_mlp(PairArgs a) {
       d = a.prec[p];
     }
     // radial inputs, channels 8h .. 8h+7
-    const float fc = valid ? 0.5f * (1.f + cosf(PI_F * d.w / a.rc)) : 0.f;
+    const float fc = valid ? 0.5f * (1.f + __cosf(PI_F * d.w / a.rc)) : 0.f;
     bf16x8 gb;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const float q = (d.w - (R0 + (8 * h + e) * a.w)) * a.inv_w;
-      gb[e] = (bf16)(expf(-q * q) * fc);
+      gb[e] = (bf16)(__expf(-q * q) * fc);
     }
-    if (a.g16 && valid) *(bf16x8*)(a.g16 + (int64_t)p * 16 + 8 * h) = gb;
+    if (DUMP && valid) *(bf16x8*)(a.g16 + (int64_t)p * 16 + 8 * h) = gb;
 
     // layer 1: Z1^T = W1b^T G^T + (A_i + A_j + b1)
     f32x16 acc[4];
@@ -502,7 +527,7 @@ __global__ __launch_bounds__(256) void k_pair_mlp(PairArgs a) {
 #pragma unroll
           for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)fmaxf(acc[b][8 * ks + e], 0.f);
       bf16* dump = layer == 0 ? a.h1 : a.h2;
-      if (dump && valid) {
+      if (DUMP && valid) {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -534,7 +559,7 @@ __global__ __launch_bounds__(256) void k_pair_mlp(PairArgs a) {
         ps = fmaf(w4s[2 * f], v, ps);
         pt = fmaf(w4s[2 * f + 1], v, pt);
       }
-    if (a.h3 && valid) {
+    if (DUMP && valid) {
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -588,9 +613,12 @@ __global__ __launch_bounds__(256) void k_mol(MolArgs a) {
       if (a.with_lj) {
         const double dx = (double)d.x, dy = (double)d.y, dz = (double)d.z;
         const double r2 = dx * dx + dy * dy + dz * dz;
-        const double s2 = a.sig2 / r2;
+        double ir2 = __builtin_amdgcn_rcp(r2);  // refined by two Newton steps
+        ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
+        ir2 = fma(ir2, fma(-r2, ir2, 1.0), ir2);
+        const double s2 = a.sig2 * ir2;
         const double s6 = s2 * s2 * s2, s12 = s6 * s6;
-        const double f = a.eps24 * (2.0 * s12 - s6) / r2 * (double)sg;
+        const double f = a.eps24 * (2.0 * s12 - s6) * ir2 * (double)sg;
         lx += f * dx;
         ly += f * dy;
         lz += f * dz;
@@ -774,7 +802,7 @@ __global__ __launch_bounds__(256) void k_dout(DoutArgs a) {
   const float4 gi = a.gF[ij.x], gj = a.gF[ij.y];
   const float ds = ((gi.x - gj.x) * d.x + (gi.y - gj.y) * d.y + (gi.z - gj.z) * d.z) * ir;
   const float t = a.st[p].y;
-  const float sig = 1.f / (1.f + expf(-t));
+  const float sig = 1.f / (1.f + __expf(-t));
   const float dt = (a.ge[ij.x] + a.ge[ij.y]) * sig;
   if (fg == 0) {
     a.dout[2 * p] = ds;
@@ -965,7 +993,10 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   a.n_up = buf<int32_t>(ctx, B_SN_UP);
   a.nb_start = buf<int32_t>(ctx, B_SN_START);
   a.up_start = buf<int32_t>(ctx, B_SN_UPSTART);
+  hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256) < 4096 ? blocks_for(n, 256) : 4096), dim3(256), 0, st,
+                     a.n_all, n);
   hipLaunchKernelGGL(k_nb_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_nb_total, dim3(blocks_for(n, 256)), dim3(256), 0, st, a.n_up, (int32_t)n, a.n_all);
   if ((e = launch_scan(st, a.n_all, buf<int32_t>(ctx, B_SN_START), n, buf<int32_t>(ctx, B_SN_TILE))) != hipSuccess)
     return hip_fail(ctx, e, "scan");
   if ((e = launch_scan(st, a.n_up, buf<int32_t>(ctx, B_SN_UPSTART), n, buf<int32_t>(ctx, B_SN_TILE))) != hipSuccess)
@@ -1054,7 +1085,10 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   const int64_t tiles = (G.np + 31) / 32;
   int64_t grid = 2 * (int64_t)dev_cu;
   if (grid * 4 > tiles) grid = (tiles + 3) / 4;
-  hipLaunchKernelGGL(k_pair_mlp, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
+  if (dump)
+    hipLaunchKernelGGL(k_pair_mlp<true>, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
+  else
+    hipLaunchKernelGGL(k_pair_mlp<false>, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "pair MLP launch");
   return ATM3_OK;
