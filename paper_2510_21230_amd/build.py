@@ -22,6 +22,7 @@ SOURCES = {
     "atm3_forces.hip": [],
     "atm3_surrogate.hip": [],
     "atm3_md.hip": [],
+    "atm3_variants.hip": [],
 }
 
 COMMON = [

@@ -108,10 +108,12 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if (p->variant < ATM3_VARIANT_3C08 || p->variant > ATM3_VARIANT_3C01)
     return fail(ctx, ATM3_EINVAL, "variant must be 3c08, 3c18 or 3c01");
   if (p->terms < 1 || p->terms > 3) return fail(ctx, ATM3_EINVAL, "terms must be a non-empty OR of ATM3_TERM_*");
-  if (p->truncation != ATM3_TRUNC_PAIR || p->variant != ATM3_VARIANT_3C08)
-    return fail(ctx, ATM3_EINVAL, "only the pairwise cutoff with the 3c08 cell sets is implemented");
   if (!make_grid(box, p->rc, g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range (floor(L/rc) < 1 or too many cells)");
-  int need = 3;
+  // cell offsets must equal minimum images for every visited set: 3 cells
+  // per dimension for the pairwise cutoff (5 for 3c18, whose base cell is
+  // chosen by lexicographic order of offsets spanning two steps), 5 for the
+  // product cutoff with 3c08, 7 with 3c18 or 3c01
+  int need = (p->variant == ATM3_VARIANT_3C18) ? 5 : 3;
   if (p->truncation == ATM3_TRUNC_PRODUCT) need = (p->variant == ATM3_VARIANT_3C08) ? 5 : 7;
   for (int d = 0; d < 3; ++d)
     if (g->n[d] < need)
@@ -260,7 +262,12 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
   if (!forces || !out_dev) return fail(ctx, ATM3_EINVAL, "forces / result pointer is NULL");
   hipError_t e = launch_binning(ctx, pos, n, g);
   if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
-  e = launch_forces(ctx, pos, n, g, *params, forces, out_dev);
+  if (params->truncation == ATM3_TRUNC_PRODUCT) {
+    e = launch_onesided(ctx, pos, n, g, *params, forces, out_dev);
+  } else {
+    e = launch_forces(ctx, pos, n, g, *params, forces, out_dev);
+    if (e == hipSuccess && params->variant != ATM3_VARIANT_3C08) e = launch_variant_counts(ctx, g, *params, out_dev);
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "force launch");
   return ATM3_OK;
 }
@@ -275,7 +282,10 @@ int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const doubl
   if (e != hipSuccess) return hip_fail(ctx, e, "result copy");
   *out = *ctx->hres;
   if (out->status == ATM3_EOVERFLOW)
-    return fail(ctx, out->status, "a 2x2x2 block of cells holds more than 512 molecules");
+    return fail(ctx, out->status,
+                params->truncation == ATM3_TRUNC_PRODUCT
+                    ? "a molecule has more than 2048 candidate partners in its neighbour cells"
+                    : "a 2x2x2 block of cells holds more than 512 molecules");
   if (out->status == ATM3_ERANGE)
     return fail(ctx, out->status, "a force contribution or sum reached 2^31 (fixed-point accumulator range)");
   if (out->status != ATM3_OK) return fail(ctx, out->status, "evaluation failed");

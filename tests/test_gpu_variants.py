@@ -1,0 +1,81 @@
+"""The product cutoff and the 3c18 / 3c01 cell sets on the GPU against the
+O(N^3) oracle: forces (1e-5 in the norm of the exact path), energies and
+virials (1e-6 relative), pair / triplet / candidate counts exact."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_21230_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+RC, NU = 2.5, 0.073
+
+# (truncation, variant, box side, molecules): boxes hold the cells each
+# combination needs (3 / 5 for 3c18 under the pairwise cutoff; 5 for the
+# product cutoff with 3c08, 7 with 3c18 and 3c01)
+CASES = [
+    ("pair", "3c18", 13.0, 1000),
+    ("pair", "3c01", 8.0, 330),
+    ("pair", "3c01", 13.0, 1000),
+    ("product", "3c08", 13.0, 700),
+    ("product", "3c18", 18.0, 900),
+    ("product", "3c01", 18.0, 900),
+]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def force_err(fg, fr):
+    nref = np.linalg.norm(fr, axis=1)
+    frms = float(np.sqrt(np.mean(nref ** 2)))
+    return float(np.max(np.linalg.norm(fg - fr, axis=1) / np.maximum(nref, frms)))
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_variant_against_brute_force(torch_cuda, orc, case):
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    trunc, var, L, n = CASES[case]
+    box = np.array([L, L, L])
+    pos, _ = workloads.rsa(n, box, dmin=0.85, seed=workloads.SEED_BASE + 700 + case)
+    _say(f"[{trunc} {var}] n={len(pos)} box={L}")
+    ref = orc.brute(pos, box, rc=RC, nu=NU, truncation=trunc, variant=var)
+    f, r = atm3.compute_forces(torch.from_numpy(pos).cuda(), box, nu=NU, truncation=trunc, variant=var)
+    torch.cuda.synchronize()
+    fg = f.cpu().numpy().astype(np.float64)
+    err = force_err(fg, ref.forces)
+    _say(f"  force err {err:.2e}; triplets {r['n_triplets']} (ref {ref.n_triplets}); candidates "
+         f"{r['n_candidates']} (ref {ref.n_candidates})")
+    assert r["n_pairs"] == ref.n_pairs
+    assert r["n_triplets"] == ref.n_triplets
+    assert r["n_candidates"] == ref.n_candidates
+    assert err <= 1e-5
+    assert r["e_lj"] == pytest.approx(ref.e_lj, rel=1e-6)
+    assert r["w_lj"] == pytest.approx(ref.w_lj, rel=1e-6)
+    assert r["e_atm"] == pytest.approx(ref.e_atm, rel=1e-6)
+    assert r["w_atm"] == pytest.approx(ref.w_atm, rel=1e-6)
+
+
+def test_small_boxes_are_rejected(torch_cuda):
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    pos, box = workloads.uniform(300, [11.0, 11.0, 11.0], seed=5)
+    p = torch.from_numpy(pos).cuda()
+    _say("[variant boxes]")
+    with pytest.raises(ValueError, match="box too small"):
+        atm3.compute_forces(p, box, variant="3c18")  # 4 cells < 5
+    with pytest.raises(ValueError, match="box too small"):
+        atm3.compute_forces(p, box, truncation="product")  # 4 cells < 5
