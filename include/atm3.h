@@ -58,7 +58,8 @@ extern "C" {
 #define ATM3_TERM_ATM 2
 
 /* Flags. */
-#define ATM3_FLAG_CHECK_FINITE 2 /* reject non-finite positions with ATM3_ERANGE */
+#define ATM3_FLAG_CHECK_FINITE 2 /* reject non-finite positions with ATM3_ERANGE
+                                    (the check blocks until it has run)      */
 
 typedef struct atm3_ctx atm3_ctx;
 

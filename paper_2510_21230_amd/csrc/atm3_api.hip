@@ -108,6 +108,7 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if (p->variant < ATM3_VARIANT_3C08 || p->variant > ATM3_VARIANT_3C01)
     return fail(ctx, ATM3_EINVAL, "variant must be 3c08, 3c18 or 3c01");
   if (p->terms < 1 || p->terms > 3) return fail(ctx, ATM3_EINVAL, "terms must be a non-empty OR of ATM3_TERM_*");
+  if (p->flags & ~ATM3_FLAG_CHECK_FINITE) return fail(ctx, ATM3_EINVAL, "unknown bits in flags");
   if (!make_grid(box, p->rc, g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range (floor(L/rc) < 1 or too many cells)");
   // cell offsets must equal minimum images for every visited set: 3 cells
   // per dimension for the pairwise cutoff (5 for 3c18, whose base cell is
@@ -135,6 +136,16 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if ((r = ensure(ctx, B_DEFER, 4 * (C + 2)))) return r;
   if ((r = ensure(ctx, B_RED, reduce_scratch_bytes()))) return r;
   if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
+  if (p->flags & ATM3_FLAG_CHECK_FINITE) {
+    int32_t* bad = (int32_t*)ctx->s.p[B_DEFER];
+    hipError_t e = launch_check_finite(ctx->stream, pos, n, bad);
+    if (e == hipSuccess) e = hipMemcpyAsync(ctx->hres, bad, 4, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finite check");
+    int32_t flag = 0;
+    memcpy(&flag, ctx->hres, 4);
+    if (flag) return fail(ctx, ATM3_ERANGE, "a position is not finite");
+  }
   return ATM3_OK;
 }
 

@@ -205,4 +205,19 @@ hipError_t launch_scan(hipStream_t st, const int32_t* count, int32_t* start, int
   return hipGetLastError();
 }
 
+namespace {
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x, int64_t m, int32_t* __restrict__ bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) bad[0] = 1;
+}
+}  // namespace
+
+hipError_t launch_check_finite(hipStream_t st, const double* pos, int64_t n, int32_t* bad_dev) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, bad_dev, (int64_t)1, 0);
+  unsigned nb = blocks_for(3 * n, 256);
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_nonfinite, dim3(nb), dim3(256), 0, st, pos, 3 * n, bad_dev);
+  return hipGetLastError();
+}
+
 }  // namespace atm3

@@ -95,16 +95,14 @@ __device__ __forceinline__ u64 to_fix(double d, int* bad) {
   return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)(uint32_t)lo;
 }
 
-// FP32 variant, branch-free: magnitude split exactly into integer and
-// fraction (both exact in FP32), then the two's-complement negation.
+// FP32 variant, branch-free: the value widened to FP64 and split as in
+// to_fix; the out-of-range test only flags (the kernel reports ERANGE).
 __device__ __forceinline__ u64 to_fix_f(float x, int* bad) {
-  const float a = fabsf(x);
-  *bad |= !(a < 2147483648.f);
-  const float fl = floorf(a);
-  const uint32_t hi = (uint32_t)fl;
-  const uint32_t lo = (uint32_t)((a - fl) * 4294967296.f);
-  const u64 v = ((u64)hi << 32) | (u64)lo;
-  return (x < 0.f) ? (u64)0 - v : v;
+  *bad |= !(fabsf(x) < 2147483648.f);
+  const double d = (double)x;
+  const double hi = floor(d);
+  const uint32_t lo = (uint32_t)((d - hi) * 4294967296.0);
+  return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)lo;
 }
 
 __device__ __forceinline__ void add_fix_f(u64* ax, u64* ay, u64* az, int m, float x, float y, float z, int* bad) {
@@ -546,14 +544,13 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       float4 pi = L.sp[ci], pj = L.sp[cj];
       float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f;
       for (int t = T0; t < T1; ++t) {
-        int k;
-        if (K0) {
-          k = __builtin_ctzll(K0);
-          K0 &= K0 - 1;
-        } else {
-          k = 64 + __builtin_ctzll(K1);
-          K1 &= K1 - 1;
-        }
+        // next set bit of (K0, K1), branch-free
+        const bool low = K0 != 0ull;
+        const u64 kw = low ? K0 : K1;
+        const int k = __builtin_ctzll(kw) + (low ? 0 : 64);
+        const u64 kr = kw & (kw - 1ull);
+        K0 = low ? kr : K0;
+        K1 = low ? K1 : kr;
         const float4 pk = L.sp[k];
         const Trip r = atm_triplet(pi, pj, pk, a.k3nu, a.k15nu, a.k075nu);
         eu += r.eu;

@@ -119,6 +119,9 @@ bool make_grid(const double box[3], double rc, Grid* g);
 // B_SORTED from the FP64 positions.
 hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g);
 
+// Sets bad_dev[0] to 1 if any of the 3n coordinates is not finite.
+hipError_t launch_check_finite(hipStream_t st, const double* pos, int64_t n, int32_t* bad_dev);
+
 // Exclusive prefix sum of count[0..n) into start[0..n], start[n] = total;
 // tile_sum needs n/1024 + 2 entries.
 hipError_t launch_scan(hipStream_t st, const int32_t* count, int32_t* start, int64_t n, int32_t* tile_sum);

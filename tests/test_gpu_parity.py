@@ -255,6 +255,13 @@ def test_invalid_arguments(torch_cuda):
         atm3.compute_forces(p, [10.0, 10.0, 10.0], rc=-1.0)
     with pytest.raises(ValueError):
         atm3.compute_forces(p.float(), [10.0, 10.0, 10.0])
+    bad = pos.copy()
+    bad[7, 1] = np.nan
+    with pytest.raises(atm3.Atm3Error, match="not finite"):
+        atm3.compute_forces(torch.from_numpy(bad).to("cuda:0"), [10.0, 10.0, 10.0], check_finite=True)
+    ok, _ = workloads.rsa(100, [10.0, 10.0, 10.0], dmin=0.9, seed=6)
+    f, r = atm3.compute_forces(torch.from_numpy(ok).to("cuda:0"), [10.0, 10.0, 10.0], check_finite=True)
+    assert r["status"] == 0 and r["n_pairs"] > 0
 
 
 def test_block_overflow_is_reported(torch_cuda):
