@@ -71,74 +71,94 @@ struct NbArgs {
   float4* prec;
 };
 
-// Visit the neighbours t of slot s that s lists as the pair's first member:
-// the molecules of its own cell with a larger slot and all molecules of the
-// 13 forward neighbour cells (offsets after (0,0,0) in z, y, x order), so
-// that every pair is found exactly once; fixed order of cells and of slots
-// within a cell.  The distance comes from the cell-centred FP64 records;
-// inside a 1e-9 relative band around rc^2 the decision is the exact
-// minimum-image expression on the input positions.
-template <class F>
-__device__ __forceinline__ void for_half_shell(const NbArgs& a, int s, F&& f) {
-  const double4 me = a.sorted[s];
-  const int orig = (int)me.w;
-  const int c = a.cell_of[orig];
-  const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
-  for (int q = 13; q < 27; ++q) {
+// Pairs listed first by each slot s: the molecules of its own cell with a
+// larger slot and all molecules of the 13 forward neighbour cells (offsets
+// after (0,0,0) in z, y, x order), so that every pair is found exactly once;
+// every pair also counts for its second slot.  One wave per cell: the lanes
+// run over the concatenated candidates of the cell's 14 half-shell cells (in
+// that order, slots ascending within a cell), one molecule s of the cell at
+// a time, and the ballot of the accepted lanes gives the count and, in the
+// fill pass, the pair numbers in candidate order.  The distance comes from
+// the cell-centred FP64 records; inside a 1e-9 relative band around rc^2 the
+// decision is the exact minimum-image expression on the input positions.
+constexpr int NB_WAVES = 4;
+
+template <bool FILL>
+__global__ __launch_bounds__(64 * NB_WAVES) void k_nb_cells(NbArgs a, int64_t ncells) {
+  __shared__ int32_t cs[NB_WAVES][14], cpre[NB_WAVES][15];
+  __shared__ double co[NB_WAVES][14][3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * NB_WAVES + w;
+  if (c >= ncells) return;  // wave-uniform; no block barriers below
+  const int cx = (int)(c % a.nx), cy = (int)((c / a.nx) % a.ny), cz = (int)(c / ((int64_t)a.nx * a.ny));
+  if (lane < 14) {
+    const int q = 13 + lane;
     const int dz = q / 9 - 1, dy = (q / 3) % 3 - 1, dx = q % 3 - 1;
-    int uz = cz + dz;
+    int uz = cz + dz, uy = cy + dy, ux = cx + dx;
     uz = uz < 0 ? uz + a.nz : (uz >= a.nz ? uz - a.nz : uz);
-    int uy = cy + dy;
     uy = uy < 0 ? uy + a.ny : (uy >= a.ny ? uy - a.ny : uy);
-    int ux = cx + dx;
     ux = ux < 0 ? ux + a.nx : (ux >= a.nx ? ux - a.nx : ux);
     const int cc = (uz * a.ny + uy) * a.nx + ux;
-    const double ox = dx * a.side[0], oy = dy * a.side[1], oz = dz * a.side[2];
-    const int t1 = a.start[cc + 1];
-    for (int t = (q == 13) ? s + 1 : a.start[cc]; t < t1; ++t) {
-      const double4 o = a.sorted[t];
-      // r_s - r_t = loc_s - loc_t - offset of t's cell
-      const double ex = (me.x - o.x) - ox, ey = (me.y - o.y) - oy, ez = (me.z - o.z) - oz;
-      const double r2 = ex * ex + ey * ey + ez * ez;
-      bool in;
-      if (r2 < a.lo2) in = true;
-      else if (r2 >= a.hi2) in = false;
-      else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
-      if (in) f(t, ex, ey, ez, r2);
-    }
+    cs[w][lane] = a.start[cc];
+    cpre[w][lane + 1] = a.start[cc + 1] - a.start[cc];
+    co[w][lane][0] = dx * a.side[0];
+    co[w][lane][1] = dy * a.side[1];
+    co[w][lane][2] = dz * a.side[2];
   }
-}
-
-// Pairs listed first by each slot; every pair also counts for its second slot.
-__global__ __launch_bounds__(256) void k_nb_count(NbArgs a) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n) return;
-  int up = 0;
-  for_half_shell(a, s, [&](int t, double, double, double, double) {
-    ++up;
-    atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
-  });
-  a.n_up[s] = up;
+  __builtin_amdgcn_wave_barrier();
+  if (lane == 0) {
+    cpre[w][0] = 0;
+    for (int q = 0; q < 14; ++q) cpre[w][q + 1] += cpre[w][q];
+  }
+  __builtin_amdgcn_wave_barrier();
+  const int total = cpre[w][14];
+  const int s0 = (int)a.start[c], s1 = (int)a.start[c + 1];
+  for (int s = s0; s < s1; ++s) {
+    const double4 me = a.sorted[s];
+    const int orig = (int)me.w;
+    int k = 0;
+    const int p0 = FILL ? a.up_start[s] : 0, e0 = FILL ? a.nb_start[s] : 0;
+    for (int base = 0; base < total; base += 64) {
+      const int idx = base + lane;
+      bool in = false;
+      int t = 0;
+      double ex = 0.0, ey = 0.0, ez = 0.0, r2 = 0.0;
+      if (idx < total) {
+        int q = 0;
+        while (idx >= cpre[w][q + 1]) ++q;
+        t = cs[w][q] + (idx - cpre[w][q]);
+        if (q != 0 || t > s) {
+          const double4 o = a.sorted[t];
+          ex = (me.x - o.x) - co[w][q][0];
+          ey = (me.y - o.y) - co[w][q][1];
+          ez = (me.z - o.z) - co[w][q][2];
+          r2 = ex * ex + ey * ey + ez * ez;
+          if (r2 < a.lo2) in = true;
+          else if (r2 >= a.hi2) in = false;
+          else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
+        }
+      }
+      const unsigned long long bits = __ballot(in);
+      if (in) {
+        if (FILL) {
+          const int pid = p0 + k + __popcll(bits & ((1ull << lane) - 1ull));
+          a.pij[pid] = make_int2(s, t);
+          a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
+          a.nb[e0 + (pid - p0)] = 2 * pid;
+        } else {
+          atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
+        }
+      }
+      k += __popcll(bits);
+    }
+    if (!FILL && lane == 0) a.n_up[s] = k;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_nb_total(const int32_t* __restrict__ n_up, int32_t n,
                                                   int32_t* __restrict__ n_all) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < n) n_all[s] += n_up[s];
-}
-
-__global__ __launch_bounds__(256) void k_nb_fill(NbArgs a) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= a.n) return;
-  int k = 0;
-  const int p0 = a.up_start[s], e0 = a.nb_start[s];
-  for_half_shell(a, s, [&](int t, double ex, double ey, double ez, double r2) {
-    const int pid = p0 + k;
-    a.pij[pid] = make_int2(s, t);
-    a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
-    a.nb[e0 + k] = 2 * pid;
-    ++k;
-  });
 }
 
 // Second-slot entries: appended in any order, then sorted per slot.
@@ -587,19 +607,22 @@ struct MolArgs {
   float* err_out;  // input order (or NULL)
   float4* f3s;     // slot order surrogate force (or NULL)
   float* es;       // slot order error estimate (or NULL)
-  int32_t* queue;  // [0] count, [1..] slots (or NULL: no fallback)
+  int32_t* flag;   // per slot: 1 if the slot takes the exact fallback (or NULL)
   double* red;     // per block: sum (s12 - s6), sum (2 s12 - s6)
 };
 
+// One wave per slot: the lanes take the slot's neighbour entries (coalesced
+// list reads), a wave reduction sums them.
 __global__ __launch_bounds__(256) void k_mol(MolArgs a) {
   __shared__ double r0[4], r1[4];
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s = blockIdx.x * 4 + wave;
   double elj = 0.0, wlj = 0.0;
   if (s < a.n) {
     float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
     double lx = 0.0, ly = 0.0, lz = 0.0;
     const int e1 = a.nb_start[s + 1];
-    for (int q = a.nb_start[s]; q < e1; ++q) {
+    for (int q = a.nb_start[s] + lane; q < e1; q += 64) {
       const int v = a.nb[q];
       const int pid = v >> 1;
       const float4 d = a.prec[pid];
@@ -628,23 +651,32 @@ __global__ __launch_bounds__(256) void k_mol(MolArgs a) {
         }
       }
     }
-    const int orig = (int)a.sorted[s].w;
-    const bool fall = a.queue && e > a.thr;
-    if (a.forces) {
-      a.forces[3 * (int64_t)orig + 0] = (float)(lx + (fall ? 0.0 : (double)fx));
-      a.forces[3 * (int64_t)orig + 1] = (float)(ly + (fall ? 0.0 : (double)fy));
-      a.forces[3 * (int64_t)orig + 2] = (float)(lz + (fall ? 0.0 : (double)fz));
+    for (int off = 32; off > 0; off >>= 1) {
+      fx += __shfl_xor(fx, off);
+      fy += __shfl_xor(fy, off);
+      fz += __shfl_xor(fz, off);
+      e += __shfl_xor(e, off);
+      if (a.with_lj) {
+        lx += __shfl_xor(lx, off);
+        ly += __shfl_xor(ly, off);
+        lz += __shfl_xor(lz, off);
+      }
     }
-    if (a.err_out) a.err_out[orig] = e;
-    if (a.f3s) a.f3s[s] = make_float4(fx, fy, fz, 0.f);
-    if (a.es) a.es[s] = e;
-    if (fall) {
-      const int qq = atomicAdd(&a.queue[0], 1);
-      a.queue[1 + qq] = s;
+    if (lane == 0) {
+      const int orig = (int)a.sorted[s].w;
+      const bool fall = a.flag && e > a.thr;
+      if (a.forces) {
+        a.forces[3 * (int64_t)orig + 0] = (float)(lx + (fall ? 0.0 : (double)fx));
+        a.forces[3 * (int64_t)orig + 1] = (float)(ly + (fall ? 0.0 : (double)fy));
+        a.forces[3 * (int64_t)orig + 2] = (float)(lz + (fall ? 0.0 : (double)fz));
+      }
+      if (a.err_out) a.err_out[orig] = e;
+      if (a.f3s) a.f3s[s] = make_float4(fx, fy, fz, 0.f);
+      if (a.es) a.es[s] = e;
+      if (a.flag) a.flag[s] = fall ? 1 : 0;
     }
   }
   if (a.red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int off = 32; off > 0; off >>= 1) {
       elj += __shfl_xor(elj, off);
       wlj += __shfl_xor(wlj, off);
@@ -857,13 +889,34 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, float* __re
   P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Fixed-order sum of per-block FP64 partials (cols interleaved) into out.
-__global__ void k_sum_rows(const double* __restrict__ part, int32_t rows, int32_t cols, double* __restrict__ out) {
-  const int c = threadIdx.x;
-  if (c >= cols) return;
-  double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += part[(int64_t)r * cols + c];
-  out[c] = s;
+// Fixed-order sum of per-block FP64 partials (rows of `cols` values,
+// cols <= 4) into out: each thread sums a strided set of rows, then a tree in
+// LDS; the order depends only on the row count.
+__global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int32_t rows, int32_t cols,
+                                                  double* __restrict__ out) {
+  __shared__ double t[4][256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < cols; ++c) {
+    double s = 0.0;
+    for (int r = tid; r < rows; r += 256) s += part[(int64_t)r * cols + c];
+    t[c][tid] = s;
+  }
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half)
+      for (int c = 0; c < cols; ++c) t[c][tid] += t[c][tid + half];
+    __syncthreads();
+  }
+  if (tid < cols) out[tid] = t[tid][0];
+}
+
+// Fallback queue from the per-slot flags: queue[0] = count, then the flagged
+// slots in slot order (positions from an exclusive scan of the flags).
+__global__ __launch_bounds__(256) void k_queue(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos,
+                                               int32_t n, int32_t* __restrict__ queue) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n && flag[s]) queue[1 + pos[s]] = s;
+  if (s == 0) queue[0] = pos[n];
 }
 
 }  // namespace
@@ -995,7 +1048,8 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   a.up_start = buf<int32_t>(ctx, B_SN_UPSTART);
   hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256) < 4096 ? blocks_for(n, 256) : 4096), dim3(256), 0, st,
                      a.n_all, n);
-  hipLaunchKernelGGL(k_nb_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+  const unsigned cell_blocks = blocks_for(G->g.ncells, NB_WAVES);
+  hipLaunchKernelGGL(k_nb_cells<false>, dim3(cell_blocks), dim3(64 * NB_WAVES), 0, st, a, G->g.ncells);
   hipLaunchKernelGGL(k_nb_total, dim3(blocks_for(n, 256)), dim3(256), 0, st, a.n_up, (int32_t)n, a.n_all);
   if ((e = launch_scan(st, a.n_all, buf<int32_t>(ctx, B_SN_START), n, buf<int32_t>(ctx, B_SN_TILE))) != hipSuccess)
     return hip_fail(ctx, e, "scan");
@@ -1017,7 +1071,7 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   a.nb = buf<int32_t>(ctx, B_SN_NB);
   a.pij = buf<int2>(ctx, B_SP_IJ);
   a.prec = buf<float4>(ctx, B_SP_REC);
-  hipLaunchKernelGGL(k_nb_fill, dim3(blocks_for(n, 256)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_nb_cells<true>, dim3(cell_blocks), dim3(64 * NB_WAVES), 0, st, a, G->g.ncells);
   hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256) < 4096 ? blocks_for(n, 256) : 4096), dim3(256), 0, st,
                      buf<int32_t>(ctx, B_SN_LOFILL), n);
   if (P > 0)
@@ -1098,7 +1152,7 @@ int sur_mol(atm3_ctx* ctx, const SurGeom& G, const atm3_params* p, float thr, bo
             float* err_out, bool keep_slot) {
   int r;
   const size_t N = (size_t)G.n;
-  const unsigned nb = blocks_for(G.n, 256);
+  const unsigned nb = blocks_for(G.n, 4);  // k_mol: one wave per slot
   if ((r = ensure(ctx, B_SRED, 16 * (size_t)nb + 64))) return r;
   if ((r = ensure(ctx, B_SQ, 4 * (N + 1)))) return r;
   if ((r = ensure(ctx, B_SF3, 16 * N))) return r;
@@ -1118,11 +1172,19 @@ int sur_mol(atm3_ctx* ctx, const SurGeom& G, const atm3_params* p, float thr, bo
   ma.err_out = err_out;
   ma.f3s = keep_slot ? buf<float4>(ctx, B_SF3) : nullptr;
   ma.es = keep_slot ? buf<float>(ctx, B_SE) : nullptr;
-  ma.queue = queue ? buf<int32_t>(ctx, B_SQ) : nullptr;
+  ma.flag = queue ? buf<int32_t>(ctx, B_SN_LOFILL) : nullptr;  // free after the list build
   ma.red = buf<double>(ctx, B_SRED);
-  if (queue) hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, ctx->stream, ma.queue, (int64_t)1);
   hipLaunchKernelGGL(k_mol, dim3(nb), dim3(256), 0, ctx->stream, ma);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && queue) {
+    int32_t* qpos = buf<int32_t>(ctx, B_SN_UPSTART) + 0;  // reused: N+1 entries
+    // the pair offsets of B_SN_UPSTART are no longer needed once the lists exist
+    e = launch_scan(ctx->stream, ma.flag, qpos, G.n, buf<int32_t>(ctx, B_SN_TILE));
+    if (e == hipSuccess)
+      hipLaunchKernelGGL(k_queue, dim3(blocks_for(G.n, 256)), dim3(256), 0, ctx->stream, ma.flag, qpos,
+                         (int32_t)G.n, buf<int32_t>(ctx, B_SQ));
+    if (e == hipSuccess) e = hipGetLastError();
+  }
   if (e != hipSuccess) return hip_fail(ctx, e, "force assembly launch");
   return ATM3_OK;
 }
@@ -1201,7 +1263,7 @@ int do_grad(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const doub
   la.ge = buf<float>(ctx, B_SGE);
   la.red = buf<double>(ctx, B_SRED);
   hipLaunchKernelGGL(k_loss, dim3(nbk), dim3(256), 0, st, la);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, st, la.red, (int32_t)nbk, 1, m->dsum);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, la.red, (int32_t)nbk, 1, m->dsum);
   if (grad) {
     if ((r = ensure(ctx, B_TDOUT, 8 * P + 8))) return r;
     if ((r = ensure(ctx, B_TDOUTB, 4 * P + 4))) return r;
@@ -1455,7 +1517,7 @@ int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t
   if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
   if ((r = sur_mol(ctx, G, p, thr, true, true, forces, err_est, false))) return r;
   hipStream_t st = ctx->stream;
-  const unsigned nbk = blocks_for(n, 256);
+  const unsigned nbk = blocks_for(n, 4);  // k_mol's partials: one row per block of four slots
   unsigned long long* ntrip = (unsigned long long*)(m->dsum + 4);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t*)ntrip, (int64_t)2);
   FallArgs fa;
@@ -1478,7 +1540,7 @@ int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t
   int dev_cu = 256;
   (void)hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
   hipLaunchKernelGGL(k_fallback, dim3(8 * dev_cu), dim3(256), 0, st, fa);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, st, buf<double>(ctx, B_SRED), (int32_t)nbk, 2, m->dsum);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, buf<double>(ctx, B_SRED), (int32_t)nbk, 2, m->dsum);
   hipError_t e = hipGetLastError();
   double sums[2];
   unsigned long long nt = 0;
