@@ -204,7 +204,7 @@ __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, doubl
     const double px = v.x + ((o & 1) ? a.half[0] : -a.half[0]);
     const double py = v.y + ((o & 2) ? a.half[1] : -a.half[1]);
     const double pz = v.z + ((o & 4) ? a.half[2] : -a.half[2]);
-    dp[t] = make_double4(px, py, pz, 0.0);
+    if (dp) dp[t] = make_double4(px, py, pz, 0.0);
     sp[t] = make_float4((float)px, (float)py, (float)pz, 0.f);
     ax[t] = 0ull;
     ay[t] = 0ull;
@@ -213,6 +213,14 @@ __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, doubl
     sorig[t] = (int32_t)v.w;
     sslot[t] = s;
   }
+}
+
+// Block-frame FP64 coordinates of a staged molecule (sorted slot s, corner
+// o), recomputed from its sorted record exactly as block_stage computes them.
+__device__ __forceinline__ double4 block_coord(const ForceArgs& a, int s, int o) {
+  const double4 v = a.sorted[s];
+  return make_double4(v.x + ((o & 1) ? a.half[0] : -a.half[0]), v.y + ((o & 2) ? a.half[1] : -a.half[1]),
+                      v.z + ((o & 4) ? a.half[2] : -a.half[2]), 0.0);
 }
 
 // Allowed-third masks: bit j of allow[c] iff (code_j & c) == 0.
@@ -318,19 +326,22 @@ struct LdsFast {
   static constexpr int NW = 2;
   static constexpr int OCAP = PCAP / 2;
   BlockHead h;
-  double4 dp[MAXB];
   float4 sp[MAXB];
   u64 ax[MAXB], ay[MAXB], az[MAXB];
   u64 mask[MAXB * NW];  // bits j > i only
   u64 allow[8 * NW];
-  u64 kset[KCAP * NW];  // K words of the non-empty pairs
-  int32_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
+  union {
+    uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
+    struct {
+      u64 kset[KCAP * NW];     // K words of the non-empty pairs (from the compaction on)
+      int32_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
+      uint16_t eij[KCAP];      // i | j << 7, non-empty pairs
+    };
+  };
   int32_t sorig[MAXB];
   int32_t sslot[MAXB];
   int32_t cnt2[2][NWAVE];
   uint16_t plist[PCAP];  // i | j << 7, all upper pairs
-  uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns
-  uint16_t eij[KCAP];    // i | j << 7, non-empty pairs
   uint8_t scode[MAXB];
 };
 
@@ -344,7 +355,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   const int n = block_cells(a, b, L.h);
   if (n > MAXB) return false;
-  block_stage(a, L.h, n, L.dp, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
+  block_stage(a, L.h, n, nullptr, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
 
@@ -449,7 +460,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         cur = i;
         fx = fy = fz = 0.0;
       }
-      const double4 di = L.dp[i], dj = L.dp[j];
+      const double4 di = block_coord(a, L.sslot[i], L.scode[i]), dj = block_coord(a, L.sslot[j], L.scode[j]);
       const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
       const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
       fx += f * ex;
