@@ -162,7 +162,6 @@ __device__ int64_t candidates_3c08(const int32_t* N) {
 struct BlockHead {
   int32_t cbase[9];
   int32_t cstart[8];
-  int32_t wsum[NWAVE];
   int32_t bad;
   double red[3][NWAVE];
   long long redi[NWAVE];
@@ -192,6 +191,12 @@ __device__ int block_cells(const ForceArgs& a, int b, BlockHead& H) {
   return H.cbase[8];
 }
 
+// Sorted slot of staged molecule t: the staging order is corner by corner.
+__device__ __forceinline__ int slot_of(const BlockHead& H, const uint8_t* scode, int t) {
+  const int o = scode[t];
+  return H.cstart[o] + (t - H.cbase[o]);
+}
+
 // Stage block-frame coordinates, corner codes, input and sorted indices, and
 // clear the force accumulators.
 __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, double4* dp, float4* sp, u64* ax,
@@ -210,8 +215,8 @@ __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, doubl
     ay[t] = 0ull;
     az[t] = 0ull;
     scode[t] = (uint8_t)o;
-    sorig[t] = (int32_t)v.w;
-    sslot[t] = s;
+    if (sorig) sorig[t] = (int32_t)v.w;
+    if (sslot) sslot[t] = s;
   }
 }
 
@@ -263,11 +268,14 @@ __device__ __forceinline__ float dist2f(const float4 p, const float4 q) {
 
 // Exact (FP64 minimum-image) cutoff test of the lanes in `maybe` for row i,
 // word w; returns the bits that pass.
-__device__ __forceinline__ u64 exact_bits(const ForceArgs& a, int i, int w, u64 maybe, const int32_t* sorig) {
+__device__ __forceinline__ u64 exact_bits(const ForceArgs& a, int i, int w, u64 maybe, const BlockHead& H,
+                                          const uint8_t* scode) {
   const int lane = threadIdx.x & 63;
   bool in = false;
-  if ((maybe >> lane) & 1ull)
-    in = exact_r2(a.pos, sorig[i], sorig[64 * w + lane], a.box[0], a.box[1], a.box[2]) < a.rc2;
+  if ((maybe >> lane) & 1ull) {
+    const int oi = (int)a.sorted[slot_of(H, scode, i)].w, oj = (int)a.sorted[slot_of(H, scode, 64 * w + lane)].w;
+    in = exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]) < a.rc2;
+  }
   return __ballot(in);
 }
 
@@ -278,7 +286,7 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int N = a.ntot;
   for (int t = tid; t < n; t += WG) {
-    const int o = scode[t], s = sslot[t];
+    const int o = scode[t], s = sslot ? sslot[t] : slot_of(H, scode, t);
     a.fpart[(int64_t)(o * 3 + 0) * N + s] = ax[t];
     a.fpart[(int64_t)(o * 3 + 1) * N + s] = ay[t];
     a.fpart[(int64_t)(o * 3 + 2) * N + s] = az[t];
@@ -338,8 +346,6 @@ struct LdsFast {
       uint16_t eij[KCAP];      // i | j << 7, non-empty pairs
     };
   };
-  int32_t sorig[MAXB];
-  int32_t sslot[MAXB];
   int32_t cnt2[2][NWAVE];
   uint16_t plist[PCAP];  // i | j << 7, all upper pairs
   uint8_t scode[MAXB];
@@ -355,7 +361,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   const int n = block_cells(a, b, L.h);
   if (n > MAXB) return false;
-  block_stage(a, L.h, n, nullptr, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
+  block_stage(a, L.h, n, nullptr, L.sp, L.ax, L.ay, L.az, L.scode, nullptr, nullptr);
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
 
@@ -380,8 +386,8 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const u64 m0 = __ballot(r0 < a.hi2) & tri & ~b0;
       const u64 m1 = __ballot(r1 < a.hi2) & ~b1;
       if (m0 | m1) {
-        b0 |= exact_bits(a, i, 0, m0, L.sorig);
-        b1 |= exact_bits(a, i, 1, m1, L.sorig);
+        b0 |= exact_bits(a, i, 0, m0, L.h, L.scode);
+        b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
       }
       if (lane == 0) {
         L.mask[i * NW + 0] = b0;
@@ -394,7 +400,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const u64 tri = ~0ull << (i - 63);
       u64 b1 = __ballot(r1 < a.lo2) & tri;
       const u64 m1 = __ballot(r1 < a.hi2) & tri & ~b1;
-      if (m1) b1 |= exact_bits(a, i, 1, m1, L.sorig);
+      if (m1) b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
       if (lane == 0) {
         L.mask[i * NW + 0] = 0ull;
         L.mask[i * NW + 1] = b1;
@@ -460,7 +466,8 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         cur = i;
         fx = fy = fz = 0.0;
       }
-      const double4 di = block_coord(a, L.sslot[i], L.scode[i]), dj = block_coord(a, L.sslot[j], L.scode[j]);
+      const double4 di = block_coord(a, slot_of(L.h, L.scode, i), L.scode[i]),
+                    dj = block_coord(a, slot_of(L.h, L.scode, j), L.scode[j]);
       const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
       const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
       fx += f * ex;
@@ -598,7 +605,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     e_atm = (double)eu;
   }
   __syncthreads();
-  block_flush(a, b, n, L.scode, L.sslot, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, bad);
+  block_flush(a, b, n, L.scode, nullptr, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, bad);
   return true;
 }
 
@@ -622,6 +629,7 @@ struct LdsBig {
   uint32_t plist[PCAP];   // i | j << 10
   int32_t pcnt[PCAP];     // triplets per pair -> offsets
   uint32_t tlist[TCAP];   // i | j << 10 | k << 20
+  int32_t wsum[NWAVE];    // block_scan scratch
   uint8_t scode[MAXB];
 };
 
@@ -681,7 +689,7 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
   __syncthreads();
   for (int q = tid; q < n * NW; q += WG) L.pw[q] = __popcll(L.mask[q]);
   __syncthreads();
-  const int npairs = block_scan(L.pw, n * NW, L.h.wsum);
+  const int npairs = block_scan(L.pw, n * NW, L.wsum);
 
   double e_lj = 0.0, w_lj = 0.0, e_atm = 0.0;
   long long n_pair = 0;
@@ -738,7 +746,7 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
     __syncthreads();
     if (!do_atm) continue;
 
-    const int ntr = block_scan(L.pcnt, np, L.h.wsum);
+    const int ntr = block_scan(L.pcnt, np, L.wsum);
     n_trip += ntr;
     for (int tr = 0; tr < ntr; tr += TCAP) {
       const int nt = (ntr - tr < TCAP) ? ntr - tr : TCAP;
