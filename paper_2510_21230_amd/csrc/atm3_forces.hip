@@ -342,7 +342,7 @@ struct LdsFast {
     uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
     struct {
       u64 kset[KCAP * NW];     // K words of the non-empty pairs (from the compaction on)
-      int32_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
+      uint16_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
       uint16_t eij[KCAP];      // i | j << 7, non-empty pairs
     };
   };
@@ -518,7 +518,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   double e_atm = 0.0;
   if (do_atm && ntr > 0) {
-    if (ne > KCAP) return false;  // uniform: ne is a block total
+    if (ne > KCAP || ntr > 65535) return false;  // uniform: block totals
     // 4. compact the non-empty pairs with their K words and triplet offsets
     for (int q = q0; q < q1; ++q) {
       const int e = L.plist[q];
@@ -531,12 +531,12 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         L.kset[eo * NW + 0] = K0;
         L.kset[eo * NW + 1] = K1;
         L.eij[eo] = (uint16_t)e;
-        L.eoff[eo] = to;
+        L.eoff[eo] = (uint16_t)to;
         ++eo;
         to += c;
       }
     }
-    if (tid == 0) L.eoff[ne] = ntr;
+    if (tid == 0) L.eoff[ne] = (uint16_t)ntr;
     __syncthreads();
 
     // 5. ATM: thread t takes triplets [t*m, (t+1)*m) in (pair, k) order
@@ -1021,7 +1021,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   const int per = (a.ncells + 7) / 8;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block<2048, 512>), dim3(8 * per), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL((k_block<1536, 448>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
