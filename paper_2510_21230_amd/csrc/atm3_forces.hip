@@ -341,12 +341,13 @@ struct LdsFast {
   union {
     uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
     struct {
-      u64 kset[KCAP * NW];     // K words of the non-empty pairs (from the compaction on)
-      uint16_t eoff[KCAP + 1];  // first triplet number of each non-empty pair
-      uint16_t eij[KCAP];      // i | j << 7, non-empty pairs
+      u64 kset[KCAP * NW];  // K words of the non-empty pairs, sorted by |K| (from the compaction on)
+      uint16_t eij[KCAP];   // i | j << 7, the same pairs
     };
   };
+  int32_t hist[128];  // pairs per |K|, then the class offsets
   int32_t cnt2[2][NWAVE];
+  long long cnt2e[NWAVE];
   uint16_t plist[PCAP];  // i | j << 7, all upper pairs
   uint8_t scode[MAXB];
 };
@@ -479,12 +480,14 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     n_pair = o1 - o0;
   }
 
-  // 3b. per pair (contiguous chunk per thread): count the non-empty pairs and
-  //     their owned third molecules
+  // 3b. per pair (contiguous chunk per thread): |K| of each pair; histogram of
+  //     the non-empty pairs by |K|
+  if (tid < 128) L.hist[tid] = 0;
+  __syncthreads();
   const int mp = (np + WG - 1) / WG;
   const int q0 = tid * mp < np ? tid * mp : np;
   const int q1 = q0 + mp < np ? q0 + mp : np;
-  int myne = 0, mytr = 0;
+  int mytr = 0;
   if (do_atm) {
     for (int q = q0; q < q1; ++q) {
       const int e = L.plist[q];
@@ -493,33 +496,34 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
                     __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
       mytr += c;
-      myne += (c > 0);
+      if (c) atomicAdd(&L.hist[c], 1);
     }
   }
-
-  // offsets of this thread's non-empty pairs and triplets
-  const int incl_e = wave_incl_scan(myne, lane);
-  const int incl_t = wave_incl_scan(mytr, lane);
-  if (lane == 63) {
-    L.cnt2[0][wave] = incl_e;
-    L.cnt2[1][wave] = incl_t;
+  {
+    const int wt = wave_incl_scan(mytr, lane);
+    if (lane == 63) L.cnt2[1][wave] = wt;
   }
   __syncthreads();
-  int ne = 0, ntr = 0, eo = incl_e - myne, to = incl_t - mytr;
-  for (int w = 0; w < NWAVE; ++w) {
-    const int ve = L.cnt2[0][w], vt = L.cnt2[1][w];
-    if (w < wave) {
-      eo += ve;
-      to += vt;
-    }
-    ne += ve;
-    ntr += vt;
+  // 4. offsets of the |K| classes, largest |K| first (one wave)
+  if (wave == 0) {
+    const int cA = 127 - 2 * lane, cB = 126 - 2 * lane;
+    const int hA = L.hist[cA], hB = L.hist[cB];
+    const int v = hA + hB;
+    const int incl = wave_incl_scan(v, lane);
+    L.hist[cA] = incl - v;
+    L.hist[cB] = incl - v + hA;
+    if (lane == 63) L.cnt2[0][0] = incl;
   }
+  __syncthreads();
+  int ntr = 0;
+  for (int w = 0; w < NWAVE; ++w) ntr += L.cnt2[1][w];
+  const int ne = L.cnt2[0][0];
 
   double e_atm = 0.0;
   if (do_atm && ntr > 0) {
-    if (ne > KCAP || ntr > 65535) return false;  // uniform: block totals
-    // 4. compact the non-empty pairs with their K words and triplet offsets
+    if (ne > KCAP) return false;  // uniform: block total
+    // the non-empty pairs with their K words, sorted by |K| (any order
+    // within a class; every sum below is exact, so the order is immaterial)
     for (int q = q0; q < q1; ++q) {
       const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
@@ -528,40 +532,26 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const u64 K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
       const int c = __popcll(K0) + __popcll(K1);
       if (c) {
-        L.kset[eo * NW + 0] = K0;
-        L.kset[eo * NW + 1] = K1;
-        L.eij[eo] = (uint16_t)e;
-        L.eoff[eo] = (uint16_t)to;
-        ++eo;
-        to += c;
+        const int pos = atomicAdd(&L.hist[c], 1);
+        L.kset[pos * NW + 0] = K0;
+        L.kset[pos * NW + 1] = K1;
+        L.eij[pos] = (uint16_t)e;
       }
     }
-    if (tid == 0) L.eoff[ne] = (uint16_t)ntr;
     __syncthreads();
 
-    // 5. ATM: thread t takes triplets [t*m, (t+1)*m) in (pair, k) order
-    const int m = (ntr + WG - 1) / WG;
-    const int T0 = tid * m < ntr ? tid * m : ntr;
-    const int T1 = T0 + m < ntr ? T0 + m : ntr;
-    float eu = 0.f;
-    if (T0 < T1) {
-      int lo = 0, hi = ne;  // eoff[lo] <= T0 < eoff[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (L.eoff[mid] <= T0) lo = mid;
-        else hi = mid;
-      }
-      int ep = lo;
-      u64 K0 = L.kset[ep * NW + 0], K1 = L.kset[ep * NW + 1];
-      for (int rem = T0 - L.eoff[ep]; rem > 0; --rem) {
-        if (K0) K0 &= K0 - 1;
-        else K1 &= K1 - 1;
-      }
-      int e = L.eij[ep];
-      int ci = e & 127, cj = e >> 7;
-      float4 pi = L.sp[ci], pj = L.sp[cj];
-      float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f;
-      for (int t = T0; t < T1; ++t) {
+    // 5. ATM: each thread takes whole pairs, pair tid + WG r in round r, so
+    //    the 64 pairs of a wave have similar |K| and finish together; F_i and
+    //    F_j stay in registers for a pair, F_k is added per triplet; the
+    //    pair's energy is added in fixed point
+    u64 eacc = 0ull;
+    for (int p = tid; p < ne; p += WG) {
+      const int e = L.eij[p];
+      const int ci = e & 127, cj = e >> 7;
+      u64 K0 = L.kset[p * NW + 0], K1 = L.kset[p * NW + 1];
+      const float4 pi = L.sp[ci], pj = L.sp[cj];
+      float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f, eu = 0.f;
+      while (K0 | K1) {
         // next set bit of (K0, K1), branch-free
         const bool low = K0 != 0ull;
         const u64 kw = low ? K0 : K1;
@@ -579,30 +569,21 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         ajy += r.fjy;
         ajz += r.fjz;
         add_fix_f(L.ax, L.ay, L.az, k, -(r.fix + r.fjx), -(r.fiy + r.fjy), -(r.fiz + r.fjz), &bad);
-        if ((K0 | K1) == 0 && t + 1 < T1) {  // next non-empty pair
-          ++ep;
-          K0 = L.kset[ep * NW + 0];
-          K1 = L.kset[ep * NW + 1];
-          e = L.eij[ep];
-          const int i = e & 127, j = e >> 7;
-          if (i != ci) {
-            add_fix_f(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
-            aix = aiy = aiz = 0.f;
-            ci = i;
-            pi = L.sp[i];
-          }
-          if (j != cj) {
-            add_fix_f(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
-            ajx = ajy = ajz = 0.f;
-            cj = j;
-            pj = L.sp[j];
-          }
-        }
       }
       add_fix_f(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
       add_fix_f(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
+      eacc += to_fix_f(eu, &bad);
     }
-    e_atm = (double)eu;
+    // exact block total of the energy; thread 0 carries it into the flush
+    const long long ew = wave_sum_ll((long long)eacc);
+    __syncthreads();  // every wave is past its last read of cnt2
+    if (lane == 0) L.cnt2e[wave] = ew;
+    __syncthreads();
+    if (tid == 0) {
+      long long et = 0;
+      for (int w = 0; w < NWAVE; ++w) et += L.cnt2e[w];
+      e_atm = from_fix((u64)et);
+    }
   }
   __syncthreads();
   block_flush(a, b, n, L.scode, nullptr, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, bad);
