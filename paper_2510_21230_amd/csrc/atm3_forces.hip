@@ -376,9 +376,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int n0 = n < 63 ? n : 63;  // rows with bits in word 0
     const bool two = n > 64;
-    int i = wv;
-    for (; i < n0; i += NWAVE) {
-      const float4 pi = L.sp[i];
+    auto row2 = [&](int i, const float4 pi) {
       const float r0 = dist2f(pi, pj0);
       const float r1 = two ? dist2f(pi, pj1) : 1e30f;
       const u64 tri = ~0ull << (i + 1);
@@ -394,7 +392,14 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         L.mask[i * NW + 0] = b0;
         L.mask[i * NW + 1] = b1;
       }
+    };
+    int i = wv;
+    for (; i + NWAVE < n0; i += 2 * NWAVE) {  // two rows per pass for overlap
+      const float4 pa = L.sp[i], pb = L.sp[i + NWAVE];
+      row2(i, pa);
+      row2(i + NWAVE, pb);
     }
+    for (; i < n0; i += NWAVE) row2(i, L.sp[i]);
     for (; i < n; i += NWAVE) {  // rows 63.. have bits in word 1 only
       const float4 pi = L.sp[i];
       const float r1 = dist2f(pi, pj1);
@@ -496,7 +501,10 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
                     __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
       mytr += c;
-      if (c) atomicAdd(&L.hist[c], 1);
+      if (c) {
+        atomicAdd(&L.hist[c], 1);
+        L.plist[q] = (uint16_t)(e | 0x8000);  // tag: non-empty K (entries use 14 bits)
+      }
     }
   }
   {
@@ -525,18 +533,18 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     // the non-empty pairs with their K words, sorted by |K| (any order
     // within a class; every sum below is exact, so the order is immaterial)
     for (int q = q0; q < q1; ++q) {
-      const int e = L.plist[q];
+      const int et = L.plist[q];
+      if (!(et & 0x8000)) continue;
+      const int e = et & 0x7fff;
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
       const u64 K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
       const u64 K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
       const int c = __popcll(K0) + __popcll(K1);
-      if (c) {
-        const int pos = atomicAdd(&L.hist[c], 1);
-        L.kset[pos * NW + 0] = K0;
-        L.kset[pos * NW + 1] = K1;
-        L.eij[pos] = (uint16_t)e;
-      }
+      const int pos = atomicAdd(&L.hist[c], 1);
+      L.kset[pos * NW + 0] = K0;
+      L.kset[pos * NW + 1] = K1;
+      L.eij[pos] = (uint16_t)e;
     }
     __syncthreads();
 
