@@ -156,7 +156,7 @@ def main():
     ap.add_argument("--workload", default="fcc1m", choices=["fcc1m", "fcc32k", "fcc1k", "slab20k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--surrogate-train-steps", type=int, default=600,
+    ap.add_argument("--surrogate-train-steps", type=int, default=1500,
                     help="training steps of the surrogate before its timing (0: skip the surrogate leg)")
     ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,

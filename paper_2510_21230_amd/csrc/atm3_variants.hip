@@ -332,28 +332,43 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
 // energy collected per molecule is the sum over triplets of u / nu counted
 // once per receiving molecule, so E3 = nu * sum / 3; W3 = 9 E3 (the ATM
 // potential is homogeneous of degree -9 in the positions).
-__global__ void k_onesided_final(const double* __restrict__ dpart, const unsigned long long* __restrict__ ipart,
-                                 int32_t nb, double nu, int32_t nx, int32_t ny, int32_t nz,
-                                 atm3_result* __restrict__ res) {
-  if (threadIdx.x != 0) return;
+__global__ __launch_bounds__(256) void k_onesided_final(const double* __restrict__ dpart,
+                                                        const unsigned long long* __restrict__ ipart, int32_t nb,
+                                                        double nu, int32_t nx, int32_t ny, int32_t nz,
+                                                        atm3_result* __restrict__ res) {
+  // fixed-order parallel sums: strided per thread, then a tree in LDS
+  __shared__ double sd[3][256];
+  __shared__ unsigned long long si[4][256];
+  const int tid = threadIdx.x;
   double d[3] = {0.0, 0.0, 0.0};
   unsigned long long c[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nb; ++b) {
+  for (int b = tid; b < nb; b += 256) {
     for (int k = 0; k < 3; ++k) d[k] += dpart[4 * (int64_t)b + k];
     for (int k = 0; k < 4; ++k) c[k] += ipart[4 * (int64_t)b + k];
   }
+  for (int k = 0; k < 3; ++k) sd[k][tid] = d[k];
+  for (int k = 0; k < 4; ++k) si[k][tid] = c[k];
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half) {
+      for (int k = 0; k < 3; ++k) sd[k][tid] += sd[k][tid + half];
+      for (int k = 0; k < 4; ++k) si[k][tid] += si[k][tid + half];
+    }
+    __syncthreads();
+  }
+  if (tid != 0) return;
   atm3_result r;
-  r.e_lj = d[0];
-  r.w_lj = d[1];
-  r.e_atm = nu * d[2] / 3.0;
+  r.e_lj = sd[0][0];
+  r.w_lj = sd[1][0];
+  r.e_atm = nu * sd[2][0] / 3.0;
   r.w_atm = 9.0 * r.e_atm;
-  r.n_pairs = (int64_t)c[0];
-  r.n_triplets = (int64_t)c[1];
-  r.n_candidates = (int64_t)c[2];
+  r.n_pairs = (int64_t)si[0][0];
+  r.n_triplets = (int64_t)si[1][0];
+  r.n_candidates = (int64_t)si[2][0];
   r.ncell[0] = nx;
   r.ncell[1] = ny;
   r.ncell[2] = nz;
-  r.status = c[3] ? ATM3_EOVERFLOW : ATM3_OK;
+  r.status = si[3][0] ? ATM3_EOVERFLOW : ATM3_OK;
   *res = r;
 }
 
@@ -412,7 +427,7 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   hipLaunchKernelGGL(k_onesided, dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
   e = phase_end(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(64), 0, ctx->stream, a.dpart, a.ipart, (int32_t)nb, p.nu, g.n[0],
+  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, ctx->stream, a.dpart, a.ipart, (int32_t)nb, p.nu, g.n[0],
                      g.n[1], g.n[2], res_dev);
   return hipGetLastError();
 }
