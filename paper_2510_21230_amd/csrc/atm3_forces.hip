@@ -10,33 +10,34 @@
 // three-cell sets; Sec. 3 eqs. celltriplet, twoonetriplets, carttriplets).
 //
 // Per block:
-//  1. stage block-frame coordinates (cell-centred + corner shift) in FP64,
-//     and their single rounding to FP32;
+//  1. stage FP32 block-frame coordinates (cell-centred + corner shift, from
+//     FP64) and corner codes;
 //  2. upper-triangle pair bit masks by wave ballots: bit j of row i (j > i)
 //     set iff r_ij^2 < rc^2; FP32 test with a guard band, FP64 re-check with
-//     the oracle's exact minimum-image formula inside the band; the upper
-//     pairs are listed as they are found;
-//  3. per pair (contiguous chunk per thread): LJ if the block owns the pair
-//     (FP64), and the owned third molecules
+//     the oracle's exact minimum-image formula inside the band;
+//  3. row-major lists of the upper pairs and of the pairs the block owns
+//     (one thread per mask word, offsets from one scan); LJ over the owned
+//     pairs in FP64;
+//  4. per pair the owned third molecules
 //     K(i,j) = mask_i & mask_j & allowed(code_i & code_j) & {k > j};
-//  4. the pairs with a non-empty K are compacted with their K words and
-//     the number of their first triplet;
+//     the pairs with a non-empty K are counting-sorted by |K|;
 //  5. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
-//     eq. forcepairs).  Each thread takes an equal share of the block's
-//     triplets in (pair, k) order and decodes them from the compacted
-//     pairs, so p_i, p_j and the accumulators of F_i, F_j stay in registers
-//     for a pair and only F_k is scattered per triplet;
+//     eq. forcepairs).  Each thread takes whole pairs in rounds, largest |K|
+//     first, so the lanes of a wave finish their pairs together; p_i, p_j
+//     and the accumulators of F_i, F_j stay in registers for a pair and only
+//     F_k is scattered per triplet;
 //  6. per-corner partial forces to HBM (each (corner, molecule) written by
 //     exactly one block, no global atomics); per-block energy and count
 //     partials.
-// Force accumulation is 64-bit fixed point (units of 2^-32): every FP64 (LJ)
-// or FP32 (ATM) contribution is converted exactly (truncated below 2^-32) and
-// added with LDS integer atomics, so the sums are exact and independent of
-// the order of arrival.  Blocks of more than 128 molecules take a general
-// path that materialises the triplets in rounds.  A gather kernel sums the
-// eight corner partials per molecule; two reduction kernels sum the
-// per-block partials in fixed order.  Every result is reproducible bit for
-// bit from run to run.
+// Force and energy accumulation is 64-bit fixed point (units of 2^-32):
+// every FP64 (LJ) or FP32 (ATM) contribution is converted exactly (rounded
+// down below 2^-32) and added with LDS integer atomics, so the sums are exact
+// and independent of the order of arrival.  Blocks of more than 128
+// molecules, or beyond the pair capacities, take a general path that
+// materialises the triplets in rounds.  A gather kernel sums the eight
+// corner partials per molecule; two reduction kernels sum the per-block
+// partials in fixed order.  Every result is reproducible bit for bit from
+// run to run.
 #include "atm3_internal.h"
 #include "atm3_terms.h"
 
@@ -326,7 +327,7 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
 // one wave per row; one thread per mask word then lists the upper pairs
 // (PCAP at most) and the upper pairs the block owns (PCAP/2 at most) in
 // row-major order.  The pairs with a non-empty K (about a third of them) are
-// compacted with their K words and triplet offsets, at most KCAP of them.
+// sorted by |K| with their K words, at most KCAP of them.
 // ---------------------------------------------------------------------------
 template <int PCAP, int KCAP>
 struct LdsFast {
@@ -798,10 +799,10 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
   return true;
 }
 
-// Regular blocks; blocks with more than 128 molecules or more upper pairs
-// than a pair segment holds are queued for k_block_big.  Workgroup ids are
-// spread over the 8 XCDs round-robin; consecutive ids on one XCD map to
-// consecutive base cells so neighbouring blocks share its L2.
+// Regular blocks; blocks with more than 128 molecules, more than PCAP upper
+// pairs or more than KCAP non-empty pairs are queued for k_block_big.
+// Workgroup ids are spread over the 8 XCDs round-robin; consecutive ids on
+// one XCD map to consecutive base cells so neighbouring blocks share its L2.
 template <int PCAP, int KCAP>
 __global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
   __shared__ LdsFast<PCAP, KCAP> L;
