@@ -24,11 +24,11 @@ kernels implement the same definition:
 * Adam (Kingma and Ba) with bias correction.
 
 ``bf16=True`` rounds, to bfloat16 with round-to-nearest-even, exactly the
-operands the GPU feeds its BF16 matrix instructions (descriptors and W1a for
-A = D W1a; g and W1b; the layer inputs h1, h2 and W2, W3; in the backward
-pass h3 and dL/d(s,t) for the W4 gradient, the layer deltas and W2, W3, and
-dL/dA), so that the comparison with the kernels measures only
-accumulation order.  With ``bf16=False`` everything is FP64.
+operands the GPU feeds its BF16 matrix instructions (the descriptors, their
+pair sum and W1; g; the biases b1, b2, b3; the layer inputs h1, h2 and W2,
+W3; in the backward pass h3 and dL/d(s,t) for the W4 gradient, the layer
+deltas and W2, W3, and dL/dA), so that the comparison with the kernels
+measures only accumulation order.  With ``bf16=False`` everything is FP64.
 """
 from __future__ import annotations
 
@@ -173,13 +173,16 @@ def forward(params, D, pairs, disp, rc, bf16_ops=False):
     u = disp / r[:, None]                       # (r_i - r_j)/r
     g = radial(r, rc)
     W1a, W1b = params["W1"][:NDESC], params["W1"][NDESC:]
-    A = _q(D, q) @ _q(W1a, q)                   # per molecule, the factored first layer
     i, j = pairs[:, 0], pairs[:, 1]
-    z1 = A[i] + A[j] + _q(g, q) @ _q(W1b, q) + params["b1"]
+    # x = [D_i + D_j, g(r_ij)]; in BF16 mode the descriptor sum is formed from
+    # the BF16 descriptors (exact in FP32) and rounded once more, and the
+    # biases enter the products as BF16 values
+    dsum = _q(_q(D[i], q) + _q(D[j], q), q)
+    z1 = dsum @ _q(W1a, q) + _q(g, q) @ _q(W1b, q) + _q(params["b1"], q)
     h1 = np.maximum(z1, 0.0)
-    z2 = _q(h1, q) @ _q(params["W2"], q) + params["b2"]
+    z2 = _q(h1, q) @ _q(params["W2"], q) + _q(params["b2"], q)
     h2 = np.maximum(z2, 0.0)
-    z3 = _q(h2, q) @ _q(params["W3"], q) + params["b3"]
+    z3 = _q(h2, q) @ _q(params["W3"], q) + _q(params["b3"], q)
     h3 = np.maximum(z3, 0.0)
     out = h3 @ params["W4"] + params["b4"]
     s, t = out[:, 0], out[:, 1]

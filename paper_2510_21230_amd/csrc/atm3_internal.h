@@ -47,7 +47,6 @@ enum Buf {
   B_SP_ST,        // float2 [P]  pair outputs s, t
   B_SD,           // float [N][64] descriptors (normalised, or raw when fitting)
   B_SDB,          // bf16 [N][64]
-  B_SA,           // float [N][128] first-layer projection D W1a
   B_SQ,           // int32 [N+1] fallback queue (count, slots)
   B_SRED,         // double reduction partials
   B_SF3,          // float4 [N] surrogate three-body force per slot

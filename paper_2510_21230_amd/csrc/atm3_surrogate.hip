@@ -39,7 +39,7 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * WID, OFF_W2 = OFF_B1 + WID, OF
 static_assert(NPARAM == ATM3_MLP_NPARAM, "parameter layout");
 constexpr float R0 = 0.8f;
 constexpr float PI_F = 3.14159265358979323846f;
-constexpr int NPERM1 = 4 * 64 * 8;        // layer 1 A fragments (bf16)
+constexpr int NPERM1 = 4 * 5 * 64 * 8;    // layer 1 A fragments: 4 descriptor K-steps + 1 radial (bf16)
 constexpr int NPERM = 4 * 4 * 2 * 64 * 8;  // layers 2, 3 A fragments (bf16)
 constexpr int MAXSPLIT = 256;
 
@@ -48,6 +48,10 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 __device__ __forceinline__ f32x16 mfma32(const bf16x8 a, const bf16x8 b, const f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
+
+// max(x, 0) as one integer max on the bit pattern (floats with the sign bit
+// set, -0 included, are negative as integers); no NaN canonicalisation.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
 
 __device__ __forceinline__ float softplusf(float t) { return fmaxf(t, 0.f) + __logf(1.f + __expf(-fabsf(t))); }
 
@@ -420,10 +424,11 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ P, bf16*
     w3b[idx] = (bf16)P[OFF_W3 + idx];
   }
   if (idx < NPERM1) {
-    // [ob][lane][e]: W1b[k = 8h + e][out = 32 ob + lane % 32]
-    const int e = idx & 7, lane = (idx >> 3) & 63, ob = idx >> 9;
-    const int k = 8 * (lane >> 5) + e, out = 32 * ob + (lane & 31);
-    wp1[idx] = (bf16)P[OFF_W1 + (NDESC + k) * WID + out];
+    // [ob][ks][lane][e]: W1[in = 16 ks + 8h + e][out = 32 ob + lane % 32];
+    // K-steps 0..3 take the 64 descriptor inputs, step 4 the 16 radial ones
+    const int e = idx & 7, lane = (idx >> 3) & 63, ks = (idx >> 9) % 5, ob = (idx >> 9) / 5;
+    const int in = 16 * ks + 8 * (lane >> 5) + e, out = 32 * ob + (lane & 31);
+    wp1[idx] = (bf16)P[OFF_W1 + in * WID + out];
   }
   if (idx < NPERM) {
     // [ob][b][ks][lane][e]: input feature 32b + 16ks + 8(e/4) + 4h + e%4
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ P, bf16*
 struct PairArgs {
   const int2* pij;
   const float4* prec;
-  const float* A;  // [slot][128]
+  const bf16* Db;  // [slot][64] BF16 descriptors
   const bf16* wp1;
   const bf16* wp2;
   const bf16* wp3;
@@ -460,36 +465,41 @@ __device__ __forceinline__ void dump4(bf16* dst, const f32x16& v, int base_reg) 
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
   bf16x4 t;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) t[q] = (bf16)fmaxf(v[base_reg + q], 0.f);
+  for (int q = 0; q < 4; ++q) t[q] = (bf16)relu(v[base_reg + q]);
   *(bf16x4*)dst = t;
 }
 
 template <bool DUMP>
-__global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
-  __shared__ bf16x8 w1s[4 * 64];
+__global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
+  __shared__ bf16x8 w1s[4 * 5 * 64];
   __shared__ bf16x8 w2s[32 * 64];
   __shared__ bf16x8 w3s[32 * 64];
   __shared__ float bsh[3 * WID];
   __shared__ float w4s[2 * WID];
   const int tid = threadIdx.x;
-  for (int q = tid; q < 4 * 64; q += 256) w1s[q] = ((const bf16x8*)a.wp1)[q];
-  for (int q = tid; q < 32 * 64; q += 256) {
+  for (int q = tid; q < 4 * 5 * 64; q += 512) w1s[q] = ((const bf16x8*)a.wp1)[q];
+  for (int q = tid; q < 32 * 64; q += 512) {
     w2s[q] = ((const bf16x8*)a.wp2)[q];
     w3s[q] = ((const bf16x8*)a.wp3)[q];
   }
-  for (int q = tid; q < WID; q += 256) {
+  for (int q = tid; q < WID; q += 512) {
     bsh[q] = a.P[OFF_B1 + q];
     bsh[WID + q] = a.P[OFF_B2 + q];
     bsh[2 * WID + q] = a.P[OFF_B3 + q];
   }
-  for (int q = tid; q < 2 * WID; q += 256) w4s[q] = a.P[OFF_W4 + q];
+  for (int q = tid; q < 2 * WID; q += 512) w4s[q] = a.P[OFF_W4 + q];
   const float b40 = a.P[OFF_B4], b41 = a.P[OFF_B4 + 1];
   __syncthreads();
 
   const int lane = tid & 63, wave = tid >> 6, h = lane >> 5, cn = lane & 31;
-  const float4* A4 = (const float4*)a.A;
+  // bias K-step: B operand with a single 1 at k = 0 (lanes h = 0), the A
+  // operand then carries the bias of row m at k = 0
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (bf16)((e == 0 && h == 0) ? 1.f : 0.f);
+  const f32x16 zero16 = {};
   const int ntiles = (a.np + 31) / 32;
-  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+  for (int tile = blockIdx.x * 8 + wave; tile < ntiles; tile += gridDim.x * 8) {
     // keeps the weight fragments in LDS: without it the loop-invariant LDS
     // reads are hoisted out of the tile loop into (spilled) registers
     asm volatile("" ::: "memory");
@@ -512,28 +522,33 @@ __global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
       gb[e] = (bf16)(__expf(-q * q) * fc);
     }
     if (DUMP && valid) *(bf16x8*)(a.g16 + (int64_t)p * 16 + 8 * h) = gb;
+    // descriptor inputs D_i + D_j, features 16 ks + 8h .. +7 (BF16 sum of
+    // BF16 values, exact in FP32, rounded once)
+    bf16x8 xb[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (valid) {
+        const bf16x8 di = *(const bf16x8*)(a.Db + (int64_t)i * NDESC + 16 * ks + 8 * h);
+        const bf16x8 dj = *(const bf16x8*)(a.Db + (int64_t)j * NDESC + 16 * ks + 8 * h);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[ks][e] = (bf16)((float)di[e] + (float)dj[e]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xb[ks][e] = (bf16)0.f;
+      }
+    }
 
-    // layer 1: Z1^T = W1b^T G^T + (A_i + A_j + b1)
+    // layer 1: Z1^T = W1^T X^T + b1
     f32x16 acc[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
+      bf16x8 bb;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int f0 = 32 * ob + 8 * q + 4 * h;
-        float4 s4 = make_float4(bsh[f0], bsh[f0 + 1], bsh[f0 + 2], bsh[f0 + 3]);
-        if (valid) {
-          const float4 ai = A4[(int64_t)i * 32 + (f0 >> 2)], aj = A4[(int64_t)j * 32 + (f0 >> 2)];
-          s4.x += ai.x + aj.x;
-          s4.y += ai.y + aj.y;
-          s4.z += ai.z + aj.z;
-          s4.w += ai.w + aj.w;
-        }
-        acc[ob][4 * q + 0] = s4.x;
-        acc[ob][4 * q + 1] = s4.y;
-        acc[ob][4 * q + 2] = s4.z;
-        acc[ob][4 * q + 3] = s4.w;
-      }
-      acc[ob] = mfma32(w1s[ob * 64 + lane], gb, acc[ob]);
+      for (int e = 0; e < 8; ++e) bb[e] = (bf16)((e == 0 && h == 0) ? bsh[32 * ob + cn] : 0.f);
+      f32x16 c = mfma32(bb, ones, zero16);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) c = mfma32(w1s[(ob * 5 + ks) * 64 + lane], xb[ks], c);
+      acc[ob] = mfma32(w1s[(ob * 5 + 4) * 64 + lane], gb, c);
     }
 
     // layers 2 and 3
@@ -545,7 +560,7 @@ __global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)fmaxf(acc[b][8 * ks + e], 0.f);
+          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)relu(acc[b][8 * ks + e]);
       bf16* dump = layer == 0 ? a.h1 : a.h2;
       if (DUMP && valid) {
 #pragma unroll
@@ -557,9 +572,10 @@ __global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
       const float* bl = bsh + (layer + 1) * WID;
 #pragma unroll
       for (int ob = 0; ob < 4; ++ob) {
-        f32x16 c;
+        bf16x8 bb;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) c[r] = bl[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+        for (int e = 0; e < 8; ++e) bb[e] = (bf16)((e == 0 && h == 0) ? bl[32 * ob + cn] : 0.f);
+        f32x16 c = mfma32(bb, ones, zero16);
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -575,7 +591,7 @@ __global__ __launch_bounds__(256, 2) void k_pair_mlp(PairArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int f = 32 * ob + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float v = fmaxf(acc[ob][r], 0.f);
+        const float v = relu(acc[ob][r]);
         ps = fmaf(w4s[2 * f], v, ps);
         pt = fmaf(w4s[2 * f + 1], v, pt);
       }
@@ -989,7 +1005,7 @@ T* buf(atm3_ctx* ctx, Buf b) {
   return (T*)ctx->s.p[b];
 }
 
-// Binning, neighbour lists, descriptors and the first-layer projection A.
+// Binning, neighbour lists and descriptors (FP32 and BF16).
 int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double* box, double rc, bool raw,
                 SurGeom* G) {
   if (!pos) return fail(ctx, ATM3_EINVAL, "pos is NULL");
@@ -1021,7 +1037,6 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   if ((r = ensure(ctx, B_SN_TILE, 4 * (N / 1024 + 2)))) return r;
   if ((r = ensure(ctx, B_SD, 4 * 64 * N))) return r;
   if ((r = ensure(ctx, B_SDB, 2 * 64 * N))) return r;
-  if ((r = ensure(ctx, B_SA, 4 * 128 * N))) return r;
   hipStream_t st = ctx->stream;
   hipError_t e = launch_binning(ctx, pos, n, G->g);
   if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
@@ -1093,23 +1108,6 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   da.D = buf<float>(ctx, B_SD);
   da.Db = buf<bf16>(ctx, B_SDB);
   hipLaunchKernelGGL(k_desc, dim3(blocks_for(4 * n, 256)), dim3(256), 0, st, da);
-  if (!raw) {
-    GemmArgs ga = {};
-    ga.A = da.Db;
-    ga.sam = 64;
-    ga.sak = 1;
-    ga.B = m->w1b;  // rows 0..63 of W1, [k][n]
-    ga.sbk = 128;
-    ga.sbn = 1;
-    ga.M = (int32_t)n;
-    ga.N = 128;
-    ga.K = 64;
-    ga.kchunk = 64;
-    ga.C = buf<float>(ctx, B_SA);
-    ga.scm = 128;
-    ga.scn = 1;
-    hipLaunchKernelGGL(k_gemm, dim3(blocks_for(n, 128), 4, 1), dim3(256), 0, st, ga);
-  }
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "surrogate preparation launch");
   return ATM3_OK;
@@ -1120,7 +1118,7 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   PairArgs pa;
   pa.pij = buf<int2>(ctx, B_SP_IJ);
   pa.prec = buf<float4>(ctx, B_SP_REC);
-  pa.A = buf<float>(ctx, B_SA);
+  pa.Db = buf<bf16>(ctx, B_SDB);
   pa.wp1 = m->wp1;
   pa.wp2 = m->wp2;
   pa.wp3 = m->wp3;
@@ -1137,12 +1135,12 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   int dev_cu = 256;
   (void)hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
   const int64_t tiles = (G.np + 31) / 32;
-  int64_t grid = 2 * (int64_t)dev_cu;
-  if (grid * 4 > tiles) grid = (tiles + 3) / 4;
+  int64_t grid = dev_cu;  // one 8-wave workgroup per CU: one LDS copy of the weights
+  if (grid * 8 > tiles) grid = (tiles + 7) / 8;
   if (dump)
-    hipLaunchKernelGGL(k_pair_mlp<true>, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
+    hipLaunchKernelGGL(k_pair_mlp<true>, dim3((unsigned)grid), dim3(512), 0, ctx->stream, pa);
   else
-    hipLaunchKernelGGL(k_pair_mlp<false>, dim3((unsigned)grid), dim3(256), 0, ctx->stream, pa);
+    hipLaunchKernelGGL(k_pair_mlp<false>, dim3((unsigned)grid), dim3(512), 0, ctx->stream, pa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "pair MLP launch");
   return ATM3_OK;
