@@ -11,33 +11,36 @@
 //
 // Per block:
 //  1. stage FP32 block-frame coordinates (cell-centred + corner shift, from
-//     FP64) and corner codes;
+//     FP64) with their FP32 residuals, and corner codes;
 //  2. upper-triangle pair bit masks by wave ballots: bit j of row i (j > i)
 //     set iff r_ij^2 < rc^2; FP32 test with a guard band, FP64 re-check with
 //     the oracle's exact minimum-image formula inside the band;
 //  3. row-major lists of the upper pairs and of the pairs the block owns
 //     (one thread per mask word, offsets from one scan); LJ over the owned
-//     pairs in FP64;
+//     pairs in FP64 (coordinates as FP32 value + residual);
 //  4. per pair the owned third molecules
-//     K(i,j) = mask_i & mask_j & allowed(code_i & code_j) & {k > j};
-//     the pairs with a non-empty K are counting-sorted by |K|;
+//     K(i,j) = mask_i & mask_j & allowed(code_i & code_j), all above j,
+//     as single-word work items of at most NCLS molecules each, placed in
+//     order of size by a block scan of per-thread class counts;
 //  5. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
-//     eq. forcepairs).  Each thread takes whole pairs in rounds, largest |K|
-//     first, so the lanes of a wave finish their pairs together; p_i, p_j
-//     and the accumulators of F_i, F_j stay in registers for a pair and only
-//     F_k is scattered per triplet;
+//     eq. forcepairs).  Each thread takes whole items in rounds, largest
+//     first, so the lanes of a wave finish their items together; p_i, p_j
+//     and the pair's force sums stay in registers for an item and only F_k
+//     is scattered per triplet;
 //  6. per-corner partial forces to HBM (each (corner, molecule) written by
 //     exactly one block, no global atomics); per-block energy and count
 //     partials.
 // Force and energy accumulation is 64-bit fixed point (units of 2^-32):
-// every FP64 (LJ) or FP32 (ATM) contribution is converted exactly (rounded
-// down below 2^-32) and added with LDS integer atomics, so the sums are exact
+// every contribution is converted to an integer number of units (rounded to
+// nearest on this path, |value| < 2^18; rounded down on the general path,
+// |value| < 2^31) and added with LDS integer atomics, so the sums are exact
 // and independent of the order of arrival.  Blocks of more than 128
-// molecules, or beyond the pair capacities, take a general path that
-// materialises the triplets in rounds.  A gather kernel sums the eight
-// corner partials per molecule; two reduction kernels sum the per-block
-// partials in fixed order.  Every result is reproducible bit for bit from
-// run to run.
+// molecules, beyond the capacities, or with a value outside the range of
+// this path take a general path that materialises the triplets in rounds.
+// Wave scans and sums use DPP lane moves, which leave the LDS to the
+// atomics.  A gather kernel sums the eight corner partials per molecule; two
+// reduction kernels sum the per-block partials in fixed order.  Every result
+// is reproducible bit for bit from run to run.
 #include "atm3_internal.h"
 #include "atm3_terms.h"
 
@@ -96,22 +99,6 @@ __device__ __forceinline__ u64 to_fix(double d, int* bad) {
   return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)(uint32_t)lo;
 }
 
-// FP32 variant, branch-free: the value widened to FP64 and split as in
-// to_fix; the out-of-range test only flags (the kernel reports ERANGE).
-__device__ __forceinline__ u64 to_fix_f(float x, int* bad) {
-  *bad |= !(fabsf(x) < 2147483648.f);
-  const double d = (double)x;
-  const double hi = floor(d);
-  const uint32_t lo = (uint32_t)((d - hi) * 4294967296.0);
-  return ((u64)(uint32_t)(int32_t)hi << 32) | (u64)lo;
-}
-
-__device__ __forceinline__ void add_fix_f(u64* ax, u64* ay, u64* az, int m, float x, float y, float z, int* bad) {
-  atomicAdd(&ax[m], to_fix_f(x, bad));
-  atomicAdd(&ay[m], to_fix_f(y, bad));
-  atomicAdd(&az[m], to_fix_f(z, bad));
-}
-
 __device__ __forceinline__ double from_fix(u64 v) { return (double)(long long)v * FIX_INV; }
 
 __device__ __forceinline__ void add_fix(u64* ax, u64* ay, u64* az, int m, double x, double y, double z, int* bad) {
@@ -120,20 +107,55 @@ __device__ __forceinline__ void add_fix(u64* ax, u64* ay, u64* az, int m, double
   atomicAdd(&az[m], to_fix(z, bad));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Wave-wide inclusive prefix sums with DPP lane moves (row shifts within
+// each 16-lane row, then the row broadcasts of lanes 15 and 31); no LDS
+// traffic.  Lanes with no source lane read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_mv(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 dpp_mv64(u64 v) {
+  return ((u64)dpp_mv<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp_mv<CTRL, ROWS>((uint32_t)v);
+}
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  uint32_t x = (uint32_t)v;
+  x += dpp_mv<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_mv<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_mv<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_mv<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_mv<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_mv<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return (int)x;
+}
+__device__ __forceinline__ u64 wave_incl_scan64(u64 x) {
+  x += dpp_mv64<0x111, 0xf>(x);
+  x += dpp_mv64<0x112, 0xf>(x);
+  x += dpp_mv64<0x114, 0xf>(x);
+  x += dpp_mv64<0x118, 0xf>(x);
+  x += dpp_mv64<0x142, 0xa>(x);
+  x += dpp_mv64<0x143, 0xc>(x);
+  return x;
+}
+__device__ __forceinline__ double wave_incl_scan_d(double v) {
+  v += __longlong_as_double((long long)dpp_mv64<0x111, 0xf>((u64)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_mv64<0x112, 0xf>((u64)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_mv64<0x114, 0xf>((u64)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_mv64<0x118, 0xf>((u64)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_mv64<0x142, 0xa>((u64)__double_as_longlong(v)));
+  v += __longlong_as_double((long long)dpp_mv64<0x143, 0xc>((u64)__double_as_longlong(v)));
   return v;
+}
+__device__ __forceinline__ u64 lane63(u64 v) {
+  return ((u64)(uint32_t)__builtin_amdgcn_readlane((int)(v >> 32), 63) << 32) |
+         (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+}
+// Wave totals, in every lane (fixed summation order).
+__device__ __forceinline__ double wave_sum(double v) {
+  return __longlong_as_double((long long)lane63((u64)__double_as_longlong(wave_incl_scan_d(v))));
 }
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-  for (int off = 1; off < 64; off <<= 1) {
-    const int u = __shfl_up(v, off, 64);
-    if (lane >= off) v += u;
-  }
-  return v;
+  return (long long)lane63(wave_incl_scan64((u64)v));
 }
 
 __device__ __forceinline__ int64_t comb2(int64_t n) { return n * (n - 1) / 2; }
@@ -199,9 +221,11 @@ __device__ __forceinline__ int slot_of(const BlockHead& H, const uint8_t* scode,
 }
 
 // Stage block-frame coordinates, corner codes, input and sorted indices, and
-// clear the force accumulators.
-__device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, double4* dp, float4* sp, u64* ax,
-                            u64* ay, u64* az, uint8_t* scode, int32_t* sorig, int32_t* sslot) {
+// clear the force accumulators.  With slo, the FP32 residuals p - (float)p
+// of the coordinates are kept as well (x in sp[t].w, y and z in slo[t]), so
+// that hi + lo carries the FP64 coordinate to about 48 bits.
+__device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, double4* dp, float4* sp, float2* slo,
+                            u64* ax, u64* ay, u64* az, uint8_t* scode, int32_t* sorig, int32_t* sslot) {
   for (int t = threadIdx.x; t < n; t += WG) {
     int o = 0;
     while (o < 7 && H.cbase[o + 1] <= t) ++o;
@@ -211,7 +235,13 @@ __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, doubl
     const double py = v.y + ((o & 2) ? a.half[1] : -a.half[1]);
     const double pz = v.z + ((o & 4) ? a.half[2] : -a.half[2]);
     if (dp) dp[t] = make_double4(px, py, pz, 0.0);
-    sp[t] = make_float4((float)px, (float)py, (float)pz, 0.f);
+    const float hx = (float)px, hy = (float)py, hz = (float)pz;
+    if (slo) {
+      sp[t] = make_float4(hx, hy, hz, (float)(px - (double)hx));
+      slo[t] = make_float2((float)(py - (double)hy), (float)(pz - (double)hz));
+    } else {
+      sp[t] = make_float4(hx, hy, hz, 0.f);
+    }
     ax[t] = 0ull;
     ay[t] = 0ull;
     az[t] = 0ull;
@@ -219,14 +249,6 @@ __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, doubl
     if (sorig) sorig[t] = (int32_t)v.w;
     if (sslot) sslot[t] = s;
   }
-}
-
-// Block-frame FP64 coordinates of a staged molecule (sorted slot s, corner
-// o), recomputed from its sorted record exactly as block_stage computes them.
-__device__ __forceinline__ double4 block_coord(const ForceArgs& a, int s, int o) {
-  const double4 v = a.sorted[s];
-  return make_double4(v.x + ((o & 1) ? a.half[0] : -a.half[0]), v.y + ((o & 2) ? a.half[1] : -a.half[1]),
-                      v.z + ((o & 4) ? a.half[2] : -a.half[2]), 0.0);
 }
 
 // Allowed-third masks: bit j of allow[c] iff (code_j & c) == 0.
@@ -329,41 +351,150 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
 // row-major order.  The pairs with a non-empty K (about a third of them) are
 // sorted by |K| with their K words, at most KCAP of them.
 // ---------------------------------------------------------------------------
+// x in units of 2^-32, rounded to nearest, as a two's-complement 64-bit
+// value, for |x| < FAST_LIMIT (the caller checks the bound): adding 1.5 * 2^20
+// in FP64 leaves x * 2^32 + 2^51 in the 52 mantissa bits (the sum lies in
+// [2^20, 2^21), whose ulp is 2^-32), and one integer subtraction removes the
+// exponent field and the offset.
+constexpr float FAST_LIMIT = 262144.f;  // 2^18
+__device__ __forceinline__ u64 to_fix_m(double x) {
+  const double t = x + 1572864.0;
+  return (u64)__double_as_longlong(t) - 0x4138000000000000ull;
+}
+__device__ __forceinline__ u64 to_fix_m(float x) { return to_fix_m((double)x); }
+
+// Adds (x, y, z) with to_fix_m; *far is raised when the bound is not met
+// (NaN included).
+__device__ __forceinline__ void add_fix_m(u64* ax, u64* ay, u64* az, int m, double x, double y, double z, int* far) {
+  *far |= !(fabs(x) + fabs(y) + fabs(z) < (double)FAST_LIMIT);
+  atomicAdd(&ax[m], to_fix_m(x));
+  atomicAdd(&ay[m], to_fix_m(y));
+  atomicAdd(&az[m], to_fix_m(z));
+}
+
+// Work items hold at most NCLS third molecules: a K word of more bits is
+// cut into runs of NCLS set bits, lowest first, and a shorter last run, so
+// that the items of a wave have near-equal sizes.  Items are sorted by
+// popcount (class 1..NCLS); per-thread class counts are packed six 10-bit
+// fields to a word, which cannot overflow once the block's item total is
+// below 1024.
+constexpr int NCLS = 8;
+struct Cls {  // classes 1-6 in v0, 7-8 in v1
+  u64 v0 = 0ull, v1 = 0ull;
+  __device__ void add(int c, u64 d) {
+    const int f = c - 1;
+    const bool up = f >= 6;
+    const u64 x = d << (10 * (up ? f - 6 : f));
+    v0 += up ? 0ull : x;
+    v1 += up ? x : 0ull;
+  }
+  __device__ int get(int c) const {
+    const int f = c - 1;
+    const bool up = f >= 6;
+    return (int)(((up ? v1 : v0) >> (10 * (up ? f - 6 : f))) & 0x3ffull);
+  }
+};
+
 template <int PCAP, int KCAP>
 struct LdsFast {
   static constexpr int MAXB = 128;
   static constexpr int NW = 2;
   static constexpr int OCAP = PCAP / 2;
   BlockHead h;
-  float4 sp[MAXB];
+  float4 sp[MAXB];   // FP32 coordinates, .w = residual of x
+  float2 slo[MAXB];  // residuals of y and z
   u64 ax[MAXB], ay[MAXB], az[MAXB];
   u64 mask[MAXB * NW];  // bits j > i only
   u64 allow[8 * NW];
   union {
     uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
     struct {
-      u64 kset[KCAP * NW];  // K words of the non-empty pairs, sorted by |K| (from the compaction on)
-      uint16_t eij[KCAP];   // i | j << 7, the same pairs
+      u64 kset[KCAP];       // K bits of each work item, sorted by popcount (from the compaction on)
+      uint16_t kmeta[KCAP];  // i | j << 7 | h << 14 of the same items: bit 0 of K is molecule j + 1 + 64 h
     };
   };
-  int32_t hist[128];  // pairs per |K|, then the class offsets
+  u64 cntw[NWAVE][2];  // per-wave item counts per class (10-bit fields)
+  int32_t nitw[NWAVE];  // per-wave item totals
   int32_t cnt2[2][NWAVE];
   long long cnt2e[NWAVE];
   uint16_t plist[PCAP];  // i | j << 7, all upper pairs
   uint8_t scode[MAXB];
 };
 
+// K(i,j) shifted down so that bit 0 is molecule j + 1: the first item holds
+// molecules j+1 .. j+64, the second j+65 .. (at most 127).  Row j of the
+// masks has bits above j only, so no bit at or below j is dropped.
+__device__ __forceinline__ void k_items(u64 K0, u64 K1, int j, u64& lo, u64& hi) {
+  const int s = j + 1;  // 1 .. 128
+  if (s >= 64) {
+    lo = s < 128 ? K1 >> (s - 64) : 0ull;
+    hi = 0ull;
+  } else {
+    lo = (K0 >> s) | (K1 << (64 - s));
+    hi = K1 >> s;
+  }
+}
+
+// One ATM triplet of the pair (i, j) with third molecule k, in FP32, for the
+// per-pair accumulation of the fast path.  With c_x, c_y, c_z as in
+// atm_triplet (eq. forcepairs): F_i(j)k = c_x r_ij is summed over k as a
+// scalar (r_ij is fixed for the pair), F_i(k)j = c_y r_ik and F_j(k)i =
+// c_z r_jk are added to the pair's accumulators, and F_k = -(c_y r_ik +
+// c_z r_jk) (eq. newton3rdlaw) is returned.  x = |r_ij|^2 and ix = 1/x are
+// the pair's.  Adds the energy term without nu to *eu and raises *mx to
+// max |F_k|.
+struct PairAcc {
+  float cx, fix, fiy, fiz, fjx, fjy, fjz, eu, mx;
+};
+__device__ __forceinline__ void atm_third(const float4 pi, const float4 pj, const float4 pk, float x, float ix,
+                                          float k3nu, float k15nu, float k075nu, PairAcc& q, float& fkx, float& fky,
+                                          float& fkz) {
+  const float ikx = pi.x - pk.x, iky = pi.y - pk.y, ikz = pi.z - pk.z;
+  const float jkx = pj.x - pk.x, jky = pj.y - pk.y, jkz = pj.z - pk.z;
+  const float y = ikx * ikx + iky * iky + ikz * ikz;
+  const float z = jkx * jkx + jky * jky + jkz * jkz;
+  // eq. (atm) in squared sides, as in atm_triplet
+  const float s = x + y + z;
+  const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
+  const float AB = A * B, AC = A * C, BC = B * C;
+  const float P = AB * C;
+  const float S = AB + AC + BC;
+  const float xy = x * y, xz = x * z;
+  const float t1 = __builtin_amdgcn_rsqf(xy * z);
+  const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
+  const float u = P * t5;
+  q.eu += fmaf(0.375f, u, t3);
+  const float G = fmaf(k15nu, u, k3nu * t3);
+  const float H = k075nu * t5;
+  // 1/y = xz t2, 1/z = xy t2
+  const float cx = fmaf(G, ix, -H * fmaf(-2.f, BC, S));
+  const float cy = fmaf(G, xz * t2, -H * fmaf(-2.f, AC, S));
+  const float cz = fmaf(G, xy * t2, -H * fmaf(-2.f, AB, S));
+  q.cx += cx;
+  q.fix = fmaf(cy, ikx, q.fix);
+  q.fiy = fmaf(cy, iky, q.fiy);
+  q.fiz = fmaf(cy, ikz, q.fiz);
+  q.fjx = fmaf(cz, jkx, q.fjx);
+  q.fjy = fmaf(cz, jky, q.fjy);
+  q.fjz = fmaf(cz, jkz, q.fjz);
+  fkx = -fmaf(cy, ikx, cz * jkx);
+  fky = -fmaf(cy, iky, cz * jky);
+  fkz = -fmaf(cy, ikz, cz * jkz);
+  q.mx = fmaxf(q.mx, fmaxf(fabsf(fkx), fmaxf(fabsf(fky), fabsf(fkz))));
+}
+
 template <int PCAP, int KCAP>
 __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L) {
   constexpr int MAXB = 128, NW = 2, OCAP = PCAP / 2;
   static_assert(WG == MAXB * NW, "one thread per mask word");
+  static_assert(KCAP < 1024, "item counts are packed in 10-bit fields");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
   const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
 
   const int n = block_cells(a, b, L.h);
   if (n > MAXB) return false;
-  block_stage(a, L.h, n, nullptr, L.sp, L.ax, L.ay, L.az, L.scode, nullptr, nullptr);
+  block_stage(a, L.h, n, nullptr, L.sp, L.slo, L.ax, L.ay, L.az, L.scode, nullptr, nullptr);
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
 
@@ -430,7 +561,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     u64 wb = L.mask[tid];
     u64 wo = (ri < n) ? (wb & L.allow[L.scode[ri] * NW + rw]) : 0ull;
     const int packed = __popcll(wb) | (__popcll(wo) << 16);
-    const int incl = wave_incl_scan(packed, lane);
+    const int incl = wave_incl_scan(packed);
     if (lane == 63) L.cnt2[0][wave] = incl;
     __syncthreads();
     int pre = incl - packed, tot = 0;
@@ -457,7 +588,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   double e_lj = 0.0, w_lj = 0.0;
   long long n_pair = 0;
-  int bad = 0;
+  int far = 0;  // a value beyond FAST_LIMIT: the block goes to the general path
   // 3a. LJ over the owned pairs (contiguous chunk per thread, FP64)
   if (do_lj) {
     const int mo = (no + WG - 1) / WG;
@@ -469,120 +600,188 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       const int e = L.olist[q];
       const int i = e & 127, j = e >> 7;
       if (i != cur) {
-        if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+        if (cur >= 0) add_fix_m(L.ax, L.ay, L.az, cur, fx, fy, fz, &far);
         cur = i;
         fx = fy = fz = 0.0;
       }
-      const double4 di = block_coord(a, slot_of(L.h, L.scode, i), L.scode[i]),
-                    dj = block_coord(a, slot_of(L.h, L.scode, j), L.scode[j]);
-      const double ex = di.x - dj.x, ey = di.y - dj.y, ez = di.z - dj.z;
+      const float4 hi = L.sp[i], hj = L.sp[j];
+      const float2 li = L.slo[i], lj = L.slo[j];
+      const double ex = ((double)hi.x - (double)hj.x) + ((double)hi.w - (double)hj.w);
+      const double ey = ((double)hi.y - (double)hj.y) + ((double)li.x - (double)lj.x);
+      const double ez = ((double)hi.z - (double)hj.z) + ((double)li.y - (double)lj.y);
       const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
       fx += f * ex;
       fy += f * ey;
       fz += f * ez;
-      add_fix(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &bad);
+      add_fix_m(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &far);
     }
-    if (cur >= 0) add_fix(L.ax, L.ay, L.az, cur, fx, fy, fz, &bad);
+    if (cur >= 0) add_fix_m(L.ax, L.ay, L.az, cur, fx, fy, fz, &far);
     n_pair = o1 - o0;
   }
 
-  // 3b. per pair (contiguous chunk per thread): |K| of each pair; histogram of
-  //     the non-empty pairs by |K|
-  if (tid < 128) L.hist[tid] = 0;
-  __syncthreads();
-  const int mp = (np + WG - 1) / WG;
-  const int q0 = tid * mp < np ? tid * mp : np;
-  const int q1 = q0 + mp < np ? q0 + mp : np;
-  int mytr = 0;
+  // 3b. per pair (pairs tid, tid + WG, ...): K(i,j) as one or two
+  //     single-word runs (k_items), cut into items of at most NCLS bits;
+  //     each thread counts its items per popcount class
+  int mytr = 0, myit = 0;
+  Cls cc;
   if (do_atm) {
-    for (int q = q0; q < q1; ++q) {
+    for (int q = tid; q < np; q += WG) {
       const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-      const int c = __popcll(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0)) +
-                    __popcll(L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1));
-      mytr += c;
-      if (c) {
-        atomicAdd(&L.hist[c], 1);
-        L.plist[q] = (uint16_t)(e | 0x8000);  // tag: non-empty K (entries use 14 bits)
+      u64 lo, hi;
+      k_items(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0], L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1], j,
+              lo, hi);
+      const int cl = __popcll(lo), ch = __popcll(hi);
+      mytr += cl + ch;
+      for (int h = 0; h < 2; ++h) {
+        const int c = h ? ch : cl;
+        if (!c) continue;
+        const int full = (c - 1) / NCLS;  // runs of NCLS bits, then the rest
+        cc.add(NCLS, (u64)full);
+        cc.add(c - NCLS * full, 1ull);
+        myit += full + 1;
       }
+      const int tag = (cl ? 0x4000 : 0) | (ch ? 0x8000 : 0);
+      if (tag) L.plist[q] = (uint16_t)(e | tag);  // entries use 14 bits
     }
   }
+  // 4. item offsets without atomics: a block scan of the packed counts in
+  //    thread order, classes laid out largest first; each thread's items go
+  //    to fixed slots, so the order is reproducible
+  Cls xs;
+  xs.v0 = wave_incl_scan64(cc.v0);
+  xs.v1 = wave_incl_scan64(cc.v1);
+  if (lane == 63) {
+    L.cntw[wave][0] = xs.v0;
+    L.cntw[wave][1] = xs.v1;
+  }
   {
-    const int wt = wave_incl_scan(mytr, lane);
-    if (lane == 63) L.cnt2[1][wave] = wt;
+    const int wt = wave_incl_scan(mytr), wi = wave_incl_scan(myit);
+    if (lane == 63) {
+      L.cnt2[1][wave] = wt;
+      L.nitw[wave] = wi;
+    }
   }
   __syncthreads();
-  // 4. offsets of the |K| classes, largest |K| first (one wave)
-  if (wave == 0) {
-    const int cA = 127 - 2 * lane, cB = 126 - 2 * lane;
-    const int hA = L.hist[cA], hB = L.hist[cB];
-    const int v = hA + hB;
-    const int incl = wave_incl_scan(v, lane);
-    L.hist[cA] = incl - v;
-    L.hist[cB] = incl - v + hA;
-    if (lane == 63) L.cnt2[0][0] = incl;
+  int ne = 0;
+  for (int v = 0; v < NWAVE; ++v) ne += L.nitw[v];
+  if (ne > KCAP) return false;  // uniform: block total (KCAP < 1024)
+  Cls tt;
+  xs.v0 -= cc.v0;
+  xs.v1 -= cc.v1;
+  for (int v = 0; v < NWAVE; ++v) {
+    const u64 t0 = L.cntw[v][0], t1 = L.cntw[v][1];
+    if (v < wave) {
+      xs.v0 += t0;
+      xs.v1 += t1;
+    }
+    tt.v0 += t0;
+    tt.v1 += t1;
   }
-  __syncthreads();
+  // class totals -> class starts, class NCLS first (block-uniform, scalar
+  // registers); xs becomes this thread's next slot per class
+  {
+    const u64 s0 = ((u64)__builtin_amdgcn_readfirstlane((uint32_t)(tt.v0 >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tt.v0);
+    const u64 s1 = ((u64)__builtin_amdgcn_readfirstlane((uint32_t)(tt.v1 >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tt.v1);
+    u64 b0 = 0ull, b1 = 0ull;
+    int start = 0;
+    for (int f = NCLS - 1; f >= 0; --f) {
+      const bool up = f >= 6;
+      const int sh = 10 * (up ? f - 6 : f);
+      const int tc = (int)(((up ? s1 : s0) >> sh) & 0x3ffull);
+      if (up)
+        b1 |= (u64)start << sh;
+      else
+        b0 |= (u64)start << sh;
+      start += tc;
+    }
+    xs.v0 += b0;
+    xs.v1 += b1;
+  }
   int ntr = 0;
   for (int w = 0; w < NWAVE; ++w) ntr += L.cnt2[1][w];
-  const int ne = L.cnt2[0][0];
 
   double e_atm = 0.0;
   if (do_atm && ntr > 0) {
-    if (ne > KCAP) return false;  // uniform: block total
-    // the non-empty pairs with their K words, sorted by |K| (any order
-    // within a class; every sum below is exact, so the order is immaterial)
-    for (int q = q0; q < q1; ++q) {
+    for (int q = tid; q < np; q += WG) {
       const int et = L.plist[q];
-      if (!(et & 0x8000)) continue;
-      const int e = et & 0x7fff;
+      if (!(et & 0xc000)) continue;
+      const int e = et & 0x3fff;
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-      const u64 K0 = L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0] & above(j, 0);
-      const u64 K1 = L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1] & above(j, 1);
-      const int c = __popcll(K0) + __popcll(K1);
-      const int pos = atomicAdd(&L.hist[c], 1);
-      L.kset[pos * NW + 0] = K0;
-      L.kset[pos * NW + 1] = K1;
-      L.eij[pos] = (uint16_t)e;
+      u64 lo, hi;
+      k_items(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0], L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1], j,
+              lo, hi);
+      for (int h = 0; h < 2; ++h) {
+        u64 w = h ? hi : lo;
+        const uint16_t meta = (uint16_t)(e | h << 14);
+        while (w) {
+          u64 run = w;
+          if (__popcll(w) > NCLS) {  // the lowest NCLS bits
+            u64 r = w;
+#pragma unroll
+            for (int t = 0; t < NCLS; ++t) r &= r - 1ull;
+            run = w ^ r;
+          }
+          w ^= run;
+          const int c = __popcll(run);
+          const int pos = xs.get(c);
+          xs.add(c, 1ull);
+          L.kset[pos] = run;
+          L.kmeta[pos] = meta;
+        }
+      }
     }
     __syncthreads();
 
-    // 5. ATM: each thread takes whole pairs, pair tid + WG r in round r, so
-    //    the 64 pairs of a wave have similar |K| and finish together; F_i and
-    //    F_j stay in registers for a pair, F_k is added per triplet; the
-    //    pair's energy is added in fixed point
+    // 5. ATM: each thread takes whole items, item tid + WG r in round r, so
+    //    the 64 items of a wave have similar popcounts and finish together;
+    //    the pair's sums stay in registers for an item and only F_k is
+    //    added per triplet; the item's energy is added in fixed point.  All
+    //    of it is converted with to_fix_m; a value beyond its range sends
+    //    the block to the general path.
     u64 eacc = 0ull;
+    float tmx = 0.f;  // max |F_k|, and sums of the item totals (NaN-propagating)
     for (int p = tid; p < ne; p += WG) {
-      const int e = L.eij[p];
-      const int ci = e & 127, cj = e >> 7;
-      u64 K0 = L.kset[p * NW + 0], K1 = L.kset[p * NW + 1];
+      const int m = L.kmeta[p];
+      const int ci = m & 127, cj = (m >> 7) & 127;
+      const int base = cj + 1 + ((m >> 8) & 64);  // j + 1 + 64 h
+      const float4* spk = L.sp + base;
+      u64* axk = L.ax + base;
+      u64* ayk = L.ay + base;
+      u64* azk = L.az + base;
+      u64 K = L.kset[p];
       const float4 pi = L.sp[ci], pj = L.sp[cj];
-      float aix = 0.f, aiy = 0.f, aiz = 0.f, ajx = 0.f, ajy = 0.f, ajz = 0.f, eu = 0.f;
-      while (K0 | K1) {
-        // next set bit of (K0, K1), branch-free
-        const bool low = K0 != 0ull;
-        const u64 kw = low ? K0 : K1;
-        const int k = __builtin_ctzll(kw) + (low ? 0 : 64);
-        const u64 kr = kw & (kw - 1ull);
-        K0 = low ? kr : K0;
-        K1 = low ? K1 : kr;
-        const float4 pk = L.sp[k];
-        const Trip r = atm_triplet(pi, pj, pk, a.k3nu, a.k15nu, a.k075nu);
-        eu += r.eu;
-        aix += r.fix;
-        aiy += r.fiy;
-        aiz += r.fiz;
-        ajx += r.fjx;
-        ajy += r.fjy;
-        ajz += r.fjz;
-        add_fix_f(L.ax, L.ay, L.az, k, -(r.fix + r.fjx), -(r.fiy + r.fjy), -(r.fiz + r.fjz), &bad);
+      const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
+      const float x = ijx * ijx + ijy * ijy + ijz * ijz;
+      const float ix = __builtin_amdgcn_rcpf(x);
+      PairAcc q = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, tmx};
+      while (K) {
+        const int k = __builtin_ctzll(K);
+        K &= K - 1ull;
+        float fkx, fky, fkz;
+        atm_third(pi, pj, spk[k], x, ix, a.k3nu, a.k15nu, a.k075nu, q, fkx, fky, fkz);
+        atomicAdd(&axk[k], to_fix_m(fkx));
+        atomicAdd(&ayk[k], to_fix_m(fky));
+        atomicAdd(&azk[k], to_fix_m(fkz));
       }
-      add_fix_f(L.ax, L.ay, L.az, ci, aix, aiy, aiz, &bad);
-      add_fix_f(L.ax, L.ay, L.az, cj, ajx, ajy, ajz, &bad);
-      eacc += to_fix_f(eu, &bad);
+      const float fix = fmaf(q.cx, ijx, q.fix), fiy = fmaf(q.cx, ijy, q.fiy), fiz = fmaf(q.cx, ijz, q.fiz);
+      const float fjx = fmaf(-q.cx, ijx, q.fjx), fjy = fmaf(-q.cx, ijy, q.fjy), fjz = fmaf(-q.cx, ijz, q.fjz);
+      // a NaN or infinite F_k makes F_i or F_j NaN or infinite as well
+      const float tot = fabsf(fix) + fabsf(fiy) + fabsf(fiz) + fabsf(fjx) + fabsf(fjy) + fabsf(fjz) + fabsf(q.eu);
+      tmx = fmaxf(q.mx, tot == tot ? tot : INFINITY);
+      atomicAdd(&L.ax[ci], to_fix_m(fix));
+      atomicAdd(&L.ay[ci], to_fix_m(fiy));
+      atomicAdd(&L.az[ci], to_fix_m(fiz));
+      atomicAdd(&L.ax[cj], to_fix_m(fjx));
+      atomicAdd(&L.ay[cj], to_fix_m(fjy));
+      atomicAdd(&L.az[cj], to_fix_m(fjz));
+      eacc += to_fix_m(q.eu);
     }
+    far |= !(tmx < FAST_LIMIT);
     // exact block total of the energy; thread 0 carries it into the flush
     const long long ew = wave_sum_ll((long long)eacc);
     __syncthreads();  // every wave is past its last read of cnt2
@@ -594,8 +793,8 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       e_atm = from_fix((u64)et);
     }
   }
-  __syncthreads();
-  block_flush(a, b, n, L.scode, nullptr, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, bad);
+  if (__syncthreads_or(far)) return false;  // uniform
+  block_flush(a, b, n, L.scode, nullptr, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, 0);
   return true;
 }
 
@@ -632,7 +831,7 @@ __device__ int block_scan(int32_t* data, int M, int32_t* wsum) {
   const int hi = lo + per < M ? lo + per : M;
   int s = 0;
   for (int q = lo; q < hi; ++q) s += data[q];
-  const int incl = wave_incl_scan(s, lane);
+  const int incl = wave_incl_scan(s);
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
   int wpre = 0, total = 0;
@@ -660,7 +859,7 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 
   const int n = block_cells(a, b, L.h);
   if (n > MAXB) return false;
-  block_stage(a, L.h, n, L.dp, L.sp, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
+  block_stage(a, L.h, n, L.dp, L.sp, nullptr, L.ax, L.ay, L.az, L.scode, L.sorig, L.sslot);
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
 
@@ -804,7 +1003,7 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 // Workgroup ids are spread over the 8 XCDs round-robin; consecutive ids on
 // one XCD map to consecutive base cells so neighbouring blocks share its L2.
 template <int PCAP, int KCAP>
-__global__ __launch_bounds__(WG) void k_block(ForceArgs a) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_block(ForceArgs a) {
   __shared__ LdsFast<PCAP, KCAP> L;
   const int per = (a.ncells + 7) / 8;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -1011,7 +1210,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   const int per = (a.ncells + 7) / 8;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block<1536, 448>), dim3(8 * per), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL((k_block<1536, 768>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
