@@ -122,13 +122,30 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cel
   perm[start[cell_of[i]] + rank[i]] = i;
 }
 
-// Restore input order inside each cell (atomic ranks arrive in any order):
-// insertion sort of the few entries of one cell per thread.
+// Restore input order inside each cell (atomic ranks arrive in any order).
+// A cell of at most 32 molecules is loaded into registers with independent
+// loads, and each entry goes to the slot given by the number of smaller
+// entries (the indices are distinct); a larger cell is insertion-sorted in
+// place.
 __global__ __launch_bounds__(256) void k_cellsort(const int32_t* __restrict__ start, int64_t ncells,
                                                   int32_t* __restrict__ perm) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncells) return;
-  const int32_t lo = start[c], hi = start[c + 1];
+  const int32_t lo = start[c], hi = start[c + 1], m = hi - lo;
+  if (m <= 1) return;
+  if (m <= 32) {
+    int32_t v[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) v[k] = (k < m) ? perm[lo + k] : INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+      int r = 0;
+#pragma unroll
+      for (int q = 0; q < 32; ++q) r += v[q] < v[k];
+      if (k < m) perm[lo + r] = v[k];
+    }
+    return;
+  }
   for (int32_t a = lo + 1; a < hi; ++a) {
     int32_t v = perm[a];
     int32_t b = a - 1;

@@ -404,7 +404,7 @@ struct LdsFast {
   float4 sp[MAXB];   // FP32 coordinates, .w = residual of x
   float2 slo[MAXB];  // residuals of y and z
   u64 ax[MAXB], ay[MAXB], az[MAXB];
-  u64 mask[MAXB * NW];  // bits j > i only
+  alignas(16) u64 mask[MAXB * NW];  // bits j > i only
   u64 allow[8 * NW];
   union {
     uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
@@ -500,7 +500,9 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   // 2. upper-triangle mask words, one wave per row (rows wave, wave + 4, ...).
   //    Lanes past the last molecule hold a far-away position, so only the
-  //    triangle (j > i) has to be masked.
+  //    triangle (j > i) has to be masked.  Lane l holds molecules l and
+  //    64 + l in registers; a row's position is read from them with
+  //    readlane (scalar registers), which keeps this phase off the LDS.
   {
     const float4 far4 = make_float4(1e18f, 1e18f, 1e18f, 0.f);
     const float4 pj0 = (lane < n) ? L.sp[lane] : far4;
@@ -508,6 +510,14 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const int n0 = n < 63 ? n : 63;  // rows with bits in word 0
     const bool two = n > 64;
+    auto rl = [](const float4 v, int l) {  // l wave-uniform
+      return make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
+                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)),
+                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.z), l)), 0.f);
+    };
+    auto put = [&](int i, u64 b0, u64 b1) {
+      if (lane == 0) *reinterpret_cast<ulonglong2*>(&L.mask[i * NW]) = make_ulonglong2(b0, b1);
+    };
     auto row2 = [&](int i, const float4 pi) {
       const float r0 = dist2f(pi, pj0);
       const float r1 = two ? dist2f(pi, pj1) : 1e30f;
@@ -520,36 +530,25 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         b0 |= exact_bits(a, i, 0, m0, L.h, L.scode);
         b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
       }
-      if (lane == 0) {
-        L.mask[i * NW + 0] = b0;
-        L.mask[i * NW + 1] = b1;
-      }
+      put(i, b0, b1);
     };
     int i = wv;
     for (; i + NWAVE < n0; i += 2 * NWAVE) {  // two rows per pass for overlap
-      const float4 pa = L.sp[i], pb = L.sp[i + NWAVE];
+      const float4 pa = rl(pj0, i), pb = rl(pj0, i + NWAVE);
       row2(i, pa);
       row2(i + NWAVE, pb);
     }
-    for (; i < n0; i += NWAVE) row2(i, L.sp[i]);
+    for (; i < n0; i += NWAVE) row2(i, rl(pj0, i));
     for (; i < n; i += NWAVE) {  // rows 63.. have bits in word 1 only
-      const float4 pi = L.sp[i];
+      const float4 pi = i < 64 ? rl(pj0, i) : rl(pj1, i - 64);
       const float r1 = dist2f(pi, pj1);
       const u64 tri = ~0ull << (i - 63);
       u64 b1 = __ballot(r1 < a.lo2) & tri;
       const u64 m1 = __ballot(r1 < a.hi2) & tri & ~b1;
       if (m1) b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
-      if (lane == 0) {
-        L.mask[i * NW + 0] = 0ull;
-        L.mask[i * NW + 1] = b1;
-      }
+      put(i, 0ull, b1);
     }
-    for (; i < MAXB; i += NWAVE) {
-      if (lane == 0) {
-        L.mask[i * NW + 0] = 0ull;
-        L.mask[i * NW + 1] = 0ull;
-      }
-    }
+    for (; i < MAXB; i += NWAVE) put(i, 0ull, 0ull);
   }
   __syncthreads();
 
@@ -753,14 +752,19 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       u64* axk = L.ax + base;
       u64* ayk = L.ay + base;
       u64* azk = L.az + base;
+      // odd lanes walk K from the top: neighbouring lanes often hold pairs
+      // of one row, whose K overlap, and would otherwise hit the same F_k
+      // address in the same instruction
+      const int flip = (lane & 1) ? 63 : 0;
       u64 K = L.kset[p];
+      if (flip) K = __builtin_bitreverse64(K);
       const float4 pi = L.sp[ci], pj = L.sp[cj];
       const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
       const float x = ijx * ijx + ijy * ijy + ijz * ijz;
       const float ix = __builtin_amdgcn_rcpf(x);
       PairAcc q = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, tmx};
       while (K) {
-        const int k = __builtin_ctzll(K);
+        const int k = __builtin_ctzll(K) ^ flip;
         K &= K - 1ull;
         float fkx, fky, fkz;
         atm_third(pi, pj, spk[k], x, ix, a.k3nu, a.k15nu, a.k075nu, q, fkx, fky, fkz);

@@ -282,3 +282,23 @@ def test_block_overflow_is_reported(torch_cuda):
     ref = oracle.brute(pos2, box, terms=2)
     f, r = gpu_eval(torch, pos2, box, terms=2)
     check_against(ref, f, r, terms=2)
+
+
+@pytest.mark.parametrize("terms", [3, 1])
+def test_close_pair_takes_general_path(torch_cuda, orc, terms):
+    """A pair at 0.5 sigma has an LJ force near 4e5, beyond the 2^18 range of
+    the regular blocks' rounding conversion: those blocks are redone by the
+    general path, and the result still matches the oracle."""
+    pos, _ = workloads.rsa(300, [10.0, 10.0, 10.0], dmin=0.9, seed=17)
+    box = np.array([10.0, 10.0, 10.0])
+    e = pos[1:] - pos[0]
+    e -= box * np.rint(e / box)
+    far = np.sqrt((e ** 2).sum(axis=1)) > 1.45  # room for a partner at 0.5
+    pos = np.concatenate([pos[:1], pos[1:][far]])
+    pos = np.concatenate([pos, (pos[:1] + np.array([[0.5, 0.0, 0.0]])) % box])
+    _say(f"[close pair] terms={terms} n={len(pos)}")
+    ref = orc.brute(pos, box, rc=RC, nu=NU, terms=terms)
+    assert np.abs(ref.forces).max() > 2.0 ** 18
+    f, r = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU, terms=terms)
+    assert r["status"] == 0
+    check_against(ref, f, r, terms)
