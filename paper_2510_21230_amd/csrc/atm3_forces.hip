@@ -488,6 +488,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
   constexpr int MAXB = 128, NW = 2, OCAP = PCAP / 2;
   static_assert(WG == MAXB * NW, "one thread per mask word");
   static_assert(KCAP < 1024, "item counts are packed in 10-bit fields");
+  static_assert(PCAP <= 16 * WG, "two tag bits per pair round in one word");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
   const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
@@ -622,9 +623,10 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
   //     single-word runs (k_items), cut into items of at most NCLS bits;
   //     each thread counts its items per popcount class
   int mytr = 0, myit = 0;
+  uint32_t tags = 0u;  // bit 2r (2r + 1): the thread's pair of round r has a low (high) run
   Cls cc;
   if (do_atm) {
-    for (int q = tid; q < np; q += WG) {
+    for (int q = tid, r = 0; q < np; q += WG, ++r) {
       const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
@@ -641,8 +643,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
         cc.add(c - NCLS * full, 1ull);
         myit += full + 1;
       }
-      const int tag = (cl ? 0x4000 : 0) | (ch ? 0x8000 : 0);
-      if (tag) L.plist[q] = (uint16_t)(e | tag);  // entries use 14 bits
+      tags |= (uint32_t)((cl ? 1 : 0) | (ch ? 2 : 0)) << (2 * r);
     }
   }
   // 4. item offsets without atomics: a block scan of the packed counts in
@@ -705,10 +706,10 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
 
   double e_atm = 0.0;
   if (do_atm && ntr > 0) {
-    for (int q = tid; q < np; q += WG) {
-      const int et = L.plist[q];
-      if (!(et & 0xc000)) continue;
-      const int e = et & 0x3fff;
+    for (uint32_t tg = tags; tg;) {  // only the pairs with a non-empty K
+      const int r = __builtin_ctz(tg) >> 1;
+      tg &= ~(3u << (2 * r));
+      const int e = L.plist[tid + WG * r];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
       u64 lo, hi;
