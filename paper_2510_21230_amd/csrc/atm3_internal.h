@@ -49,6 +49,7 @@ enum Buf {
   B_SDB,          // bf16 [N][64]
   B_SQ,           // int32 [N+1] fallback queue (count, slots)
   B_SRED,         // double reduction partials
+  B_SRED2,        // double [256][4] second-stage reduction partials
   B_SF3,          // float4 [N] surrogate three-body force per slot
   B_SE,           // float [N]  error estimate per slot
   B_SG,           // float4 [N] dL/dF per slot

@@ -627,18 +627,57 @@ struct MolArgs {
   double* red;     // per block: sum (s12 - s6), sum (2 s12 - s6)
 };
 
-// One wave per slot: the lanes take the slot's neighbour entries (coalesced
-// list reads), a wave reduction sums them.
+// Sums over groups of 8 lanes with DPP row shifts: afterwards lanes 7 and 15
+// of each 16-lane row hold the sums of lanes 0-7 and 8-15 of that row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <typename T>
+__device__ __forceinline__ T sum8(T v) {
+  if constexpr (sizeof(T) == 4) {
+    v += dpp_f<0x111>(v);  // row_shr:1
+    v += dpp_f<0x112>(v);  // row_shr:2
+    v += dpp_f<0x114>(v);  // row_shr:4
+  } else {
+    v += dpp_d<0x111>(v);
+    v += dpp_d<0x112>(v);
+    v += dpp_d<0x114>(v);
+  }
+  return v;
+}
+// Whole-wave sum in every lane: each 16-lane row, then the four row totals;
+// fixed order.
+__device__ __forceinline__ double wave_total(double v) {
+  v = sum8(v);
+  v += dpp_d<0x118>(v);  // row_shr:8: lane 15 of each row holds its row total
+  auto rl = [&](int l) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+  };
+  return ((rl(15) + rl(31)) + rl(47)) + rl(63);
+}
+
+// Eight lanes per slot: each takes every eighth of the slot's neighbour
+// entries, and DPP group sums combine them (no LDS traffic).
 __global__ __launch_bounds__(256) void k_mol(MolArgs a) {
   __shared__ double r0[4], r1[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int s = blockIdx.x * 4 + wave;
-  double elj = 0.0, wlj = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane & 7;
+  const int s = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 3);
+  float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
+  double lx = 0.0, ly = 0.0, lz = 0.0, elj = 0.0, wlj = 0.0;
   if (s < a.n) {
-    float fx = 0.f, fy = 0.f, fz = 0.f, e = 0.f;
-    double lx = 0.0, ly = 0.0, lz = 0.0;
     const int e1 = a.nb_start[s + 1];
-    for (int q = a.nb_start[s] + lane; q < e1; q += 64) {
+    for (int q = a.nb_start[s] + g; q < e1; q += 8) {
       const int v = a.nb[q];
       const int pid = v >> 1;
       const float4 d = a.prec[pid];
@@ -667,36 +706,32 @@ __global__ __launch_bounds__(256) void k_mol(MolArgs a) {
         }
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      fx += __shfl_xor(fx, off);
-      fy += __shfl_xor(fy, off);
-      fz += __shfl_xor(fz, off);
-      e += __shfl_xor(e, off);
-      if (a.with_lj) {
-        lx += __shfl_xor(lx, off);
-        ly += __shfl_xor(ly, off);
-        lz += __shfl_xor(lz, off);
-      }
+  }
+  fx = sum8(fx);
+  fy = sum8(fy);
+  fz = sum8(fz);
+  e = sum8(e);
+  if (a.with_lj) {
+    lx = sum8(lx);
+    ly = sum8(ly);
+    lz = sum8(lz);
+  }
+  if (g == 7 && s < a.n) {
+    const int orig = (int)a.sorted[s].w;
+    const bool fall = a.flag && e > a.thr;
+    if (a.forces) {
+      a.forces[3 * (int64_t)orig + 0] = (float)(lx + (fall ? 0.0 : (double)fx));
+      a.forces[3 * (int64_t)orig + 1] = (float)(ly + (fall ? 0.0 : (double)fy));
+      a.forces[3 * (int64_t)orig + 2] = (float)(lz + (fall ? 0.0 : (double)fz));
     }
-    if (lane == 0) {
-      const int orig = (int)a.sorted[s].w;
-      const bool fall = a.flag && e > a.thr;
-      if (a.forces) {
-        a.forces[3 * (int64_t)orig + 0] = (float)(lx + (fall ? 0.0 : (double)fx));
-        a.forces[3 * (int64_t)orig + 1] = (float)(ly + (fall ? 0.0 : (double)fy));
-        a.forces[3 * (int64_t)orig + 2] = (float)(lz + (fall ? 0.0 : (double)fz));
-      }
-      if (a.err_out) a.err_out[orig] = e;
-      if (a.f3s) a.f3s[s] = make_float4(fx, fy, fz, 0.f);
-      if (a.es) a.es[s] = e;
-      if (a.flag) a.flag[s] = fall ? 1 : 0;
-    }
+    if (a.err_out) a.err_out[orig] = e;
+    if (a.f3s) a.f3s[s] = make_float4(fx, fy, fz, 0.f);
+    if (a.es) a.es[s] = e;
+    if (a.flag) a.flag[s] = fall ? 1 : 0;
   }
   if (a.red) {
-    for (int off = 32; off > 0; off >>= 1) {
-      elj += __shfl_xor(elj, off);
-      wlj += __shfl_xor(wlj, off);
-    }
+    elj = wave_total(elj);
+    wlj = wave_total(wlj);
     if (lane == 0) {
       r0[wave] = elj;
       r1[wave] = wlj;
@@ -906,15 +941,17 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ P, float* __re
 }
 
 // Fixed-order sum of per-block FP64 partials (rows of `cols` values,
-// cols <= 4) into out: each thread sums a strided set of rows, then a tree in
-// LDS; the order depends only on the row count.
+// cols <= 4): workgroup g sums rows [g chunk, (g + 1) chunk) into row g of
+// out, each thread a strided set of them, then a tree in LDS; the order
+// depends only on the row count.
 __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ part, int32_t rows, int32_t cols,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int32_t chunk) {
   __shared__ double t[4][256];
   const int tid = threadIdx.x;
+  const int lo = blockIdx.x * chunk, hi = lo + chunk < rows ? lo + chunk : rows;
   for (int c = 0; c < cols; ++c) {
     double s = 0.0;
-    for (int r = tid; r < rows; r += 256) s += part[(int64_t)r * cols + c];
+    for (int r = lo + tid; r < hi; r += 256) s += part[(int64_t)r * cols + c];
     t[c][tid] = s;
   }
   __syncthreads();
@@ -923,7 +960,7 @@ __global__ __launch_bounds__(256) void k_sum_rows(const double* __restrict__ par
       for (int c = 0; c < cols; ++c) t[c][tid] += t[c][tid + half];
     __syncthreads();
   }
-  if (tid < cols) out[tid] = t[tid][0];
+  if (tid < cols) out[(int64_t)blockIdx.x * cols + tid] = t[tid][0];
 }
 
 // Fallback queue from the per-slot flags: queue[0] = count, then the flagged
@@ -1146,12 +1183,27 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   return ATM3_OK;
 }
 
+// Fixed-order sum of `rows` rows of `cols` doubles into out: one workgroup
+// for short inputs, else 256 contiguous chunks, then their sums.  B_SRED2
+// must hold 256 x 4 doubles.
+void sum_rows(atm3_ctx* ctx, hipStream_t st, const double* part, int32_t rows, int32_t cols, double* out) {
+  if (rows <= 8192) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, part, rows, cols, out, rows);
+    return;
+  }
+  const int32_t chunk = (rows + 255) / 256, g1 = (rows + chunk - 1) / chunk;
+  double* tmp = buf<double>(ctx, B_SRED2);
+  hipLaunchKernelGGL(k_sum_rows, dim3(g1), dim3(256), 0, st, part, rows, cols, tmp, chunk);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, (const double*)tmp, g1, cols, out, g1);
+}
+
 int sur_mol(atm3_ctx* ctx, const SurGeom& G, const atm3_params* p, float thr, bool with_lj, bool queue, float* forces,
             float* err_out, bool keep_slot) {
   int r;
   const size_t N = (size_t)G.n;
-  const unsigned nb = blocks_for(G.n, 4);  // k_mol: one wave per slot
+  const unsigned nb = blocks_for(G.n, 32);  // k_mol: eight lanes per slot
   if ((r = ensure(ctx, B_SRED, 16 * (size_t)nb + 64))) return r;
+  if ((r = ensure(ctx, B_SRED2, 8 * 256 * 4))) return r;
   if ((r = ensure(ctx, B_SQ, 4 * (N + 1)))) return r;
   if ((r = ensure(ctx, B_SF3, 16 * N))) return r;
   if ((r = ensure(ctx, B_SE, 4 * N))) return r;
@@ -1261,7 +1313,7 @@ int do_grad(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const doub
   la.ge = buf<float>(ctx, B_SGE);
   la.red = buf<double>(ctx, B_SRED);
   hipLaunchKernelGGL(k_loss, dim3(nbk), dim3(256), 0, st, la);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, la.red, (int32_t)nbk, 1, m->dsum);
+  sum_rows(ctx, st, la.red, (int32_t)nbk, 1, m->dsum);
   if (grad) {
     if ((r = ensure(ctx, B_TDOUT, 8 * P + 8))) return r;
     if ((r = ensure(ctx, B_TDOUTB, 4 * P + 4))) return r;
@@ -1515,7 +1567,7 @@ int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t
   if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
   if ((r = sur_mol(ctx, G, p, thr, true, true, forces, err_est, false))) return r;
   hipStream_t st = ctx->stream;
-  const unsigned nbk = blocks_for(n, 4);  // k_mol's partials: one row per block of four slots
+  const unsigned nbk = blocks_for(n, 32);  // k_mol's partials: one row per block of 32 slots
   unsigned long long* ntrip = (unsigned long long*)(m->dsum + 4);
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, (int32_t*)ntrip, (int64_t)2);
   FallArgs fa;
@@ -1538,7 +1590,7 @@ int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t
   int dev_cu = 256;
   (void)hipDeviceGetAttribute(&dev_cu, hipDeviceAttributeMultiprocessorCount, ctx->device);
   hipLaunchKernelGGL(k_fallback, dim3(8 * dev_cu), dim3(256), 0, st, fa);
-  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, st, buf<double>(ctx, B_SRED), (int32_t)nbk, 2, m->dsum);
+  sum_rows(ctx, st, buf<double>(ctx, B_SRED), (int32_t)nbk, 2, m->dsum);
   hipError_t e = hipGetLastError();
   double sums[2];
   unsigned long long nt = 0;
