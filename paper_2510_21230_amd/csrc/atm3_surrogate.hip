@@ -86,6 +86,7 @@ struct NbArgs {
 // the cell-centred FP64 records; inside a 1e-9 relative band around rc^2 the
 // decision is the exact minimum-image expression on the input positions.
 constexpr int NB_WAVES = 4;
+constexpr int NB_PASS = 4;  // candidates held in registers: up to 64 NB_PASS per cell
 
 template <bool FILL>
 __global__ __launch_bounds__(64 * NB_WAVES) void k_nb_cells(NbArgs a, int64_t ncells) {
@@ -117,43 +118,93 @@ __global__ __launch_bounds__(64 * NB_WAVES) void k_nb_cells(NbArgs a, int64_t nc
   __builtin_amdgcn_wave_barrier();
   const int total = cpre[w][14];
   const int s0 = (int)a.start[c], s1 = (int)a.start[c + 1];
+  // one candidate per lane and pass: accept it for slot s (cell-centred FP64
+  // distance, exact re-check inside the band), then count or fill by ballot
+  auto visit = [&](int s, const double4& me, int pass, int k, int t, bool own, double ox, double oy, double oz,
+                   double cx, double cy, double cz, int origc, int p0, int e0) {
+    bool in = false;
+    double ex = 0.0, ey = 0.0, ez = 0.0, r2 = 0.0;
+    if (t >= 0 && (!own || t > s)) {
+      ex = (me.x - ox) - cx;
+      ey = (me.y - oy) - cy;
+      ez = (me.z - oz) - cz;
+      r2 = ex * ex + ey * ey + ez * ez;
+      if (r2 < a.lo2) in = true;
+      else if (r2 >= a.hi2) in = false;
+      else in = exact_r2(a.pos, (int)me.w, origc, a.box[0], a.box[1], a.box[2]) < a.rc2;
+    }
+    const unsigned long long bits = __ballot(in);
+    if (in) {
+      if (FILL) {
+        const int pid = p0 + k + __popcll(bits & ((1ull << lane) - 1ull));
+        a.pij[pid] = make_int2(s, t);
+        a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
+        a.nb[e0 + (pid - p0)] = 2 * pid;
+      } else {
+        atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
+      }
+    }
+    (void)pass;
+    return k + __popcll(bits);
+  };
+  if (total <= 64 * NB_PASS) {
+    // the cell's candidates are the same for each of its molecules: resolve
+    // them once into registers
+    int tt[NB_PASS], oc[NB_PASS];
+    bool own[NB_PASS];
+    double ox[NB_PASS], oy[NB_PASS], oz[NB_PASS], cx[NB_PASS], cy[NB_PASS], cz[NB_PASS];
+#pragma unroll
+    for (int pass = 0; pass < NB_PASS; ++pass) {
+      const int idx = 64 * pass + lane;
+      tt[pass] = -1;
+      oc[pass] = 0;
+      own[pass] = false;
+      ox[pass] = oy[pass] = oz[pass] = cx[pass] = cy[pass] = cz[pass] = 0.0;
+      if (idx < total) {
+        int q = 0;
+        while (idx >= cpre[w][q + 1]) ++q;
+        const int t = cs[w][q] + (idx - cpre[w][q]);
+        const double4 o = a.sorted[t];
+        tt[pass] = t;
+        oc[pass] = (int)o.w;
+        own[pass] = q == 0;
+        ox[pass] = o.x;
+        oy[pass] = o.y;
+        oz[pass] = o.z;
+        cx[pass] = co[w][q][0];
+        cy[pass] = co[w][q][1];
+        cz[pass] = co[w][q][2];
+      }
+    }
+    const int npass = (total + 63) / 64;
+    for (int s = s0; s < s1; ++s) {
+      const double4 me = a.sorted[s];
+      int k = 0;
+      const int p0 = FILL ? a.up_start[s] : 0, e0 = FILL ? a.nb_start[s] : 0;
+#pragma unroll
+      for (int pass = 0; pass < NB_PASS; ++pass)
+        if (pass < npass)
+          k = visit(s, me, pass, k, tt[pass], own[pass], ox[pass], oy[pass], oz[pass], cx[pass], cy[pass], cz[pass],
+                    oc[pass], p0, e0);
+      if (!FILL && lane == 0) a.n_up[s] = k;
+    }
+    return;
+  }
   for (int s = s0; s < s1; ++s) {
     const double4 me = a.sorted[s];
-    const int orig = (int)me.w;
     int k = 0;
     const int p0 = FILL ? a.up_start[s] : 0, e0 = FILL ? a.nb_start[s] : 0;
     for (int base = 0; base < total; base += 64) {
       const int idx = base + lane;
-      bool in = false;
-      int t = 0;
-      double ex = 0.0, ey = 0.0, ez = 0.0, r2 = 0.0;
+      int t = -1, q = 0;
+      double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
       if (idx < total) {
-        int q = 0;
         while (idx >= cpre[w][q + 1]) ++q;
         t = cs[w][q] + (idx - cpre[w][q]);
-        if (q != 0 || t > s) {
-          const double4 o = a.sorted[t];
-          ex = (me.x - o.x) - co[w][q][0];
-          ey = (me.y - o.y) - co[w][q][1];
-          ez = (me.z - o.z) - co[w][q][2];
-          r2 = ex * ex + ey * ey + ez * ez;
-          if (r2 < a.lo2) in = true;
-          else if (r2 >= a.hi2) in = false;
-          else in = exact_r2(a.pos, orig, (int)o.w, a.box[0], a.box[1], a.box[2]) < a.rc2;
-        }
+        o = a.sorted[t];
       }
-      const unsigned long long bits = __ballot(in);
-      if (in) {
-        if (FILL) {
-          const int pid = p0 + k + __popcll(bits & ((1ull << lane) - 1ull));
-          a.pij[pid] = make_int2(s, t);
-          a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
-          a.nb[e0 + (pid - p0)] = 2 * pid;
-        } else {
-          atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
-        }
-      }
-      k += __popcll(bits);
+      k = visit(s, me, base / 64, k, t, q == 0, o.x, o.y, o.z, co[w][q][0], co[w][q][1], co[w][q][2], (int)o.w, p0,
+                e0);
     }
     if (!FILL && lane == 0) a.n_up[s] = k;
   }
