@@ -38,7 +38,6 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * WID, OFF_W2 = OFF_B1 + WID, OF
               NPARAM = OFF_B4 + 2;
 static_assert(NPARAM == ATM3_MLP_NPARAM, "parameter layout");
 constexpr float R0 = 0.8f;
-constexpr float PI_F = 3.14159265358979323846f;
 constexpr int NPERM1 = 4 * 5 * 64 * 8;    // layer 1 A fragments: 4 descriptor K-steps + 1 radial (bf16)
 constexpr int NPERM = 4 * 4 * 2 * 64 * 8;  // layers 2, 3 A fragments (bf16)
 constexpr int MAXSPLIT = 256;
@@ -284,7 +283,7 @@ struct DescArgs {
   const int32_t* nb;
   const float4* prec;
   int32_t n, raw;
-  float rc, w, inv_w;
+  float rc, w, inv_w, pi_rc;
   const float* mean;
   const float* inv_sd;
   float* D;
@@ -301,46 +300,61 @@ __global__ __launch_bounds__(256) void k_desc(DescArgs a) {
     for (int d = 0; d < 3; ++d) V[c][d] = 0.f;
     for (int d = 0; d < 6; ++d) Q[c][d] = 0.f;
   }
+  // channel 4 cg + c has q_c = (r - mu_{4cg})/w - c, so
+  // g_{c+1} = g_c exp(2 q_c - 1) and exp(2 q_{c+1} - 1) = exp(2 q_c - 1) e^-2
+  const float mu0 = R0 + (float)(4 * cg) * a.w;
+  const float em2 = 0.1353352832366127f;  // e^-2
+  const float third = 1.f / 3.f;
   const int e1 = a.nb_start[s + 1];
   for (int e = a.nb_start[s]; e < e1; ++e) {
     const int v = a.nb[e];
     const float4 d = a.prec[v >> 1];
     // u = (r_other - r_s)/r: -(r_i - r_j)/r when s is the pair's first slot
-    const float sg = (v & 1) ? 1.f : -1.f;
-    const float ir = 1.f / d.w;
-    const float ux = sg * d.x * ir, uy = sg * d.y * ir, uz = sg * d.z * ir;
-    const float fc = 0.5f * (1.f + __cosf(PI_F * d.w / a.rc));
-    const float third = 1.f / 3.f;
+    const float sir = ((v & 1) ? 1.f : -1.f) * __builtin_amdgcn_rcpf(d.w);
+    const float ux = d.x * sir, uy = d.y * sir, uz = d.z * sir;
+    const float fc = 0.5f * (1.f + __cosf(d.w * a.pi_rc));
+    const float q0 = (d.w - mu0) * a.inv_w;
+    float g = __expf(-q0 * q0) * fc;
+    float E = __expf(fmaf(2.f, q0, -1.f));
+    const float qxx = ux * ux - third, qyy = uy * uy - third, qzz = uz * uz - third;
+    const float qxy = ux * uy, qxz = ux * uz, qyz = uy * uz;
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int ch = 4 * cg + c;
-      const float q = (d.w - (R0 + ch * a.w)) * a.inv_w;
-      const float g = __expf(-q * q) * fc;
       S[c] += g;
-      V[c][0] += g * ux;
-      V[c][1] += g * uy;
-      V[c][2] += g * uz;
-      Q[c][0] += g * (ux * ux - third);
-      Q[c][1] += g * (uy * uy - third);
-      Q[c][2] += g * (uz * uz - third);
-      Q[c][3] += g * (ux * uy);
-      Q[c][4] += g * (ux * uz);
-      Q[c][5] += g * (uy * uz);
+      V[c][0] = fmaf(g, ux, V[c][0]);
+      V[c][1] = fmaf(g, uy, V[c][1]);
+      V[c][2] = fmaf(g, uz, V[c][2]);
+      Q[c][0] = fmaf(g, qxx, Q[c][0]);
+      Q[c][1] = fmaf(g, qyy, Q[c][1]);
+      Q[c][2] = fmaf(g, qzz, Q[c][2]);
+      Q[c][3] = fmaf(g, qxy, Q[c][3]);
+      Q[c][4] = fmaf(g, qxz, Q[c][4]);
+      Q[c][5] = fmaf(g, qyz, Q[c][5]);
+      g *= E;
+      E *= em2;
     }
   }
+  float f[4][4];  // [invariant k][channel c]
   for (int c = 0; c < 4; ++c) {
-    const int ch = 4 * cg + c;
     const float vx = V[c][0], vy = V[c][1], vz = V[c][2];
     const float xx = Q[c][0], yy = Q[c][1], zz = Q[c][2], xy = Q[c][3], xz = Q[c][4], yz = Q[c][5];
-    float f[4];
-    f[0] = S[c];
-    f[1] = vx * vx + vy * vy + vz * vz;
-    f[2] = xx * xx + yy * yy + zz * zz + 2.f * (xy * xy + xz * xz + yz * yz);
-    f[3] = vx * (xx * vx + xy * vy + xz * vz) + vy * (xy * vx + yy * vy + yz * vz) + vz * (xz * vx + yz * vy + zz * vz);
-    for (int k = 0; k < 4; ++k) {
-      const int col = 16 * k + ch;
-      const float x = a.raw ? f[k] : (f[k] - a.mean[col]) * a.inv_sd[col];
-      a.D[(int64_t)s * NDESC + col] = x;
-      if (a.Db) a.Db[(int64_t)s * NDESC + col] = (bf16)x;
+    f[0][c] = S[c];
+    f[1][c] = vx * vx + vy * vy + vz * vz;
+    f[2][c] = xx * xx + yy * yy + zz * zz + 2.f * (xy * xy + xz * xz + yz * yz);
+    f[3][c] = vx * (xx * vx + xy * vy + xz * vz) + vy * (xy * vx + yy * vy + yz * vz) + vz * (xz * vx + yz * vy + zz * vz);
+  }
+  // columns 16 k + 4 cg .. 16 k + 4 cg + 3: one 16-byte (8-byte) store each
+  for (int k = 0; k < 4; ++k) {
+    const int col = 16 * k + 4 * cg;
+    float x[4];
+    for (int c = 0; c < 4; ++c) x[c] = a.raw ? f[k][c] : (f[k][c] - a.mean[col + c]) * a.inv_sd[col + c];
+    if (a.D) *reinterpret_cast<float4*>(a.D + (int64_t)s * NDESC + col) = make_float4(x[0], x[1], x[2], x[3]);
+    if (a.Db) {
+      const bf16 h0 = (bf16)x[0], h1 = (bf16)x[1], h2 = (bf16)x[2], h3 = (bf16)x[3];
+      uint2 u;
+      u.x = (uint32_t)__builtin_bit_cast(uint16_t, h0) | (uint32_t)__builtin_bit_cast(uint16_t, h1) << 16;
+      u.y = (uint32_t)__builtin_bit_cast(uint16_t, h2) | (uint32_t)__builtin_bit_cast(uint16_t, h3) << 16;
+      *reinterpret_cast<uint2*>(a.Db + (int64_t)s * NDESC + col) = u;
     }
   }
 }
@@ -503,7 +517,7 @@ struct PairArgs {
   const bf16* wp3;
   const float* P;
   int32_t np;
-  float rc, w, inv_w;
+  float rc, w, inv_w, pi_rc;
   float2* st;
   bf16* h1;  // training dumps [pair][128] (or NULL)
   bf16* h2;
@@ -565,12 +579,18 @@ __global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
       d = a.prec[p];
     }
     // radial inputs, channels 8h .. 8h+7
-    const float fc = valid ? 0.5f * (1.f + __cosf(PI_F * d.w / a.rc)) : 0.f;
+    // (g_{e+1} = g_e exp(2 q_e - 1), the factor shrinking by e^-2 per channel)
+    const float fc = valid ? 0.5f * (1.f + __cosf(d.w * a.pi_rc)) : 0.f;
     bf16x8 gb;
+    {
+      const float q0 = (d.w - (R0 + (float)(8 * h) * a.w)) * a.inv_w;
+      float g = __expf(-q0 * q0) * fc, E = __expf(fmaf(2.f, q0, -1.f));
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const float q = (d.w - (R0 + (8 * h + e) * a.w)) * a.inv_w;
-      gb[e] = (bf16)(__expf(-q * q) * fc);
+      for (int e = 0; e < 8; ++e) {
+        gb[e] = (bf16)g;
+        g *= E;
+        E *= 0.1353352832366127f;  // e^-2
+      }
     }
     if (DUMP && valid) *(bf16x8*)(a.g16 + (int64_t)p * 16 + 8 * h) = gb;
     // descriptor inputs D_i + D_j, features 16 ks + 8h .. +7 (BF16 sum of
@@ -1095,7 +1115,7 @@ T* buf(atm3_ctx* ctx, Buf b) {
 
 // Binning, neighbour lists and descriptors (FP32 and BF16).
 int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const double* box, double rc, bool raw,
-                SurGeom* G) {
+                bool fp32_desc, SurGeom* G) {
   if (!pos) return fail(ctx, ATM3_EINVAL, "pos is NULL");
   if (n < 1 || n > (int64_t)1 << 26) return fail(ctx, ATM3_EINVAL, "n must be in [1, 2^26]");
   if (!box) return fail(ctx, ATM3_EINVAL, "box is NULL");
@@ -1191,9 +1211,10 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   da.rc = (float)rc;
   da.w = (float)((rc - R0) / (NR - 1));
   da.inv_w = (float)((NR - 1) / (rc - R0));
+  da.pi_rc = (float)(3.14159265358979323846 / rc);
   da.mean = m->stats;
   da.inv_sd = m->stats + 64;
-  da.D = buf<float>(ctx, B_SD);
+  da.D = fp32_desc ? buf<float>(ctx, B_SD) : nullptr;
   da.Db = buf<bf16>(ctx, B_SDB);
   hipLaunchKernelGGL(k_desc, dim3(blocks_for(4 * n, 256)), dim3(256), 0, st, da);
   e = hipGetLastError();
@@ -1215,6 +1236,7 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   pa.rc = (float)G.rc;
   pa.w = (float)((G.rc - R0) / (NR - 1));
   pa.inv_w = (float)((NR - 1) / (G.rc - R0));
+  pa.pi_rc = (float)(3.14159265358979323846 / G.rc);
   pa.st = buf<float2>(ctx, B_SP_ST);
   pa.h1 = dump ? buf<bf16>(ctx, B_TH1) : nullptr;
   pa.h2 = dump ? buf<bf16>(ctx, B_TH2) : nullptr;
@@ -1338,7 +1360,7 @@ int do_grad(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const doub
             const float* target, float lam, float* grad, double* loss_out) {
   if (!target) return fail(ctx, ATM3_EINVAL, "f3_target is NULL");
   SurGeom G;
-  int r = sur_prepare(ctx, m, pos, n, box, rc, false, &G);
+  int r = sur_prepare(ctx, m, pos, n, box, rc, false, false, &G);
   if (r) return r;
   const size_t P = (size_t)G.np, N = (size_t)n;
   if ((r = ensure(ctx, B_TH1, 2 * 128 * P))) return r;
@@ -1590,7 +1612,7 @@ int atm3_mlp_fit_stats(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n,
   int r = begin(ctx, m);
   if (r) return r;
   SurGeom G;
-  if ((r = sur_prepare(ctx, m, pos, n, box, rc, true, &G))) return r;
+  if ((r = sur_prepare(ctx, m, pos, n, box, rc, true, true, &G))) return r;
   const int chunk = 2048;
   const int parts = (int)((n + chunk - 1) / chunk);
   if ((r = ensure(ctx, B_SRED, 8 * 128 * (size_t)parts))) return r;
@@ -1614,7 +1636,7 @@ int atm3_surrogate_forces(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t
     return fail(ctx, ATM3_EINVAL, "sigma must be > 0, eps and nu finite");
   if (p->truncation != ATM3_TRUNC_PAIR) return fail(ctx, ATM3_EINVAL, "the surrogate uses the pairwise cutoff");
   SurGeom G;
-  if ((r = sur_prepare(ctx, m, pos, n, box, p->rc, false, &G))) return r;
+  if ((r = sur_prepare(ctx, m, pos, n, box, p->rc, false, false, &G))) return r;
   if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
   if ((r = sur_mol(ctx, G, p, thr, true, true, forces, err_est, false))) return r;
   hipStream_t st = ctx->stream;
@@ -1696,7 +1718,7 @@ int atm3_surrogate_pairs(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t 
   if (r) return r;
   if (cap < 0) return fail(ctx, ATM3_EINVAL, "cap must be >= 0");
   SurGeom G;
-  if ((r = sur_prepare(ctx, m, pos, n, box, rc, false, &G))) return r;
+  if ((r = sur_prepare(ctx, m, pos, n, box, rc, false, desc != nullptr, &G))) return r;
   if ((r = sur_pairs_forward(ctx, m, G, false))) return r;
   if ((r = sur_mol(ctx, G, nullptr, 0.f, false, false, nullptr, err, true))) return r;
   hipStream_t st = ctx->stream;
