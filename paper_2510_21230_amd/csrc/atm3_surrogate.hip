@@ -67,6 +67,7 @@ struct NbArgs {
   double rc2, lo2, hi2;
   int32_t* n_all;
   int32_t* n_up;
+  int32_t* lo_fill;
   const int32_t* nb_start;
   const int32_t* up_start;
   int32_t* nb;
@@ -139,6 +140,8 @@ __global__ __launch_bounds__(64 * NB_WAVES) void k_nb_cells(NbArgs a, int64_t nc
         a.pij[pid] = make_int2(s, t);
         a.prec[pid] = make_float4((float)ex, (float)ey, (float)ez, (float)sqrt(r2));
         a.nb[e0 + (pid - p0)] = 2 * pid;
+        // the second-slot entry, appended in any order (k_nb_sort orders it)
+        a.nb[a.nb_start[t] + a.n_up[t] + atomicAdd(&a.lo_fill[t], 1)] = 2 * pid + 1;
       } else {
         atomicAdd(&a.n_all[t], 1);  // n_all holds the second-slot counts here
       }
@@ -215,43 +218,31 @@ __global__ __launch_bounds__(256) void k_nb_total(const int32_t* __restrict__ n_
   if (s < n) n_all[s] += n_up[s];
 }
 
-// Second-slot entries: appended in any order, then sorted per slot.
-__global__ __launch_bounds__(256) void k_nb_lower(const int2* __restrict__ pij, int32_t P,
-                                                  const int32_t* __restrict__ nb_start,
-                                                  const int32_t* __restrict__ n_up, int32_t* __restrict__ lo_fill,
-                                                  int32_t* __restrict__ nb) {
-  const int pid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pid >= P) return;
-  const int t = pij[pid].y;
-  const int slot = nb_start[t] + n_up[t] + atomicAdd(&lo_fill[t], 1);
-  nb[slot] = 2 * pid + 1;
-}
-
-// Sort each slot's second-member entries by pair number: in LDS when they
-// fit (SORT_CAP per thread, odd stride against bank conflicts), else in place.
-constexpr int SORT_CAP = 48, SORT_STRIDE = 49;
+// Sort each slot's second-member entries by pair number.  Up to SORT_REG of
+// them are loaded into registers with independent loads and each goes to
+// the position given by the number of smaller entries (the entries are
+// distinct); longer lists are insertion-sorted in place.
+constexpr int SORT_REG = 40;
 
 __global__ __launch_bounds__(256) void k_nb_sort(const int32_t* __restrict__ nb_start,
                                                  const int32_t* __restrict__ n_up, int32_t n,
                                                  int32_t* __restrict__ nb) {
-  __shared__ int32_t lds[256 * SORT_STRIDE];
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int lo = nb_start[s] + n_up[s], hi = nb_start[s + 1];
   const int len = hi - lo;
-  if (len <= SORT_CAP) {
-    int32_t* b = lds + threadIdx.x * SORT_STRIDE;
-    for (int x = 0; x < len; ++x) b[x] = nb[lo + x];
-    for (int x = 1; x < len; ++x) {
-      const int v = b[x];
-      int y = x - 1;
-      while (y >= 0 && b[y] > v) {
-        b[y + 1] = b[y];
-        --y;
-      }
-      b[y + 1] = v;
+  if (len <= 1) return;
+  if (len <= SORT_REG) {
+    int32_t v[SORT_REG];
+#pragma unroll
+    for (int x = 0; x < SORT_REG; ++x) v[x] = x < len ? nb[lo + x] : INT32_MAX;
+#pragma unroll
+    for (int x = 0; x < SORT_REG; ++x) {
+      int r = 0;
+#pragma unroll
+      for (int y = 0; y < SORT_REG; ++y) r += v[y] < v[x];
+      if (x < len) nb[lo + r] = v[x];
     }
-    for (int x = 0; x < len; ++x) nb[lo + x] = b[x];
     return;
   }
   for (int x = lo + 1; x < hi; ++x) {
@@ -1194,12 +1185,10 @@ int sur_prepare(atm3_ctx* ctx, atm3_mlp* m, const double* pos, int64_t n, const 
   a.nb = buf<int32_t>(ctx, B_SN_NB);
   a.pij = buf<int2>(ctx, B_SP_IJ);
   a.prec = buf<float4>(ctx, B_SP_REC);
-  hipLaunchKernelGGL(k_nb_cells<true>, dim3(cell_blocks), dim3(64 * NB_WAVES), 0, st, a, G->g.ncells);
+  a.lo_fill = buf<int32_t>(ctx, B_SN_LOFILL);
   hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256) < 4096 ? blocks_for(n, 256) : 4096), dim3(256), 0, st,
-                     buf<int32_t>(ctx, B_SN_LOFILL), n);
-  if (P > 0)
-    hipLaunchKernelGGL(k_nb_lower, dim3(blocks_for(P, 256)), dim3(256), 0, st, a.pij, (int32_t)P, a.nb_start,
-                       a.n_up, buf<int32_t>(ctx, B_SN_LOFILL), a.nb);
+                     a.lo_fill, n);
+  hipLaunchKernelGGL(k_nb_cells<true>, dim3(cell_blocks), dim3(64 * NB_WAVES), 0, st, a, G->g.ncells);
   hipLaunchKernelGGL(k_nb_sort, dim3(blocks_for(n, 256)), dim3(256), 0, st, a.nb_start, a.n_up, (int32_t)n, a.nb);
 
   DescArgs da;
