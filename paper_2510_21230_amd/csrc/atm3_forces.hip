@@ -466,10 +466,11 @@ __device__ __forceinline__ void atm_third(const float4 pi, const float4 pj, cons
   q.eu += fmaf(0.375f, u, t3);
   const float G = fmaf(k15nu, u, k3nu * t3);
   const float H = k075nu * t5;
-  // 1/y = xz t2, 1/z = xy t2
-  const float cx = fmaf(G, ix, -H * fmaf(-2.f, BC, S));
-  const float cy = fmaf(G, xz * t2, -H * fmaf(-2.f, AC, S));
-  const float cz = fmaf(G, xy * t2, -H * fmaf(-2.f, AB, S));
+  // 1/y = xz t2, 1/z = xy t2; -H dP/dx = 2H BC - H S (cyclic)
+  const float Gt2 = G * t2, H2 = H + H, nHS = -H * S;
+  const float cx = fmaf(G, ix, fmaf(H2, BC, nHS));
+  const float cy = fmaf(Gt2, xz, fmaf(H2, AC, nHS));
+  const float cz = fmaf(Gt2, xy, fmaf(H2, AB, nHS));
   q.cx += cx;
   q.fix = fmaf(cy, ikx, q.fix);
   q.fiy = fmaf(cy, iky, q.fiy);
@@ -619,14 +620,19 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     n_pair = o1 - o0;
   }
 
-  // 3b. per pair (pairs tid, tid + WG, ...): K(i,j) as one or two
+  // 3b. per pair (pairs pq, pq + WG, ...): K(i,j) as one or two
   //     single-word runs (k_items), cut into items of at most NCLS bits;
   //     each thread counts its items per popcount class
   int mytr = 0, myit = 0;
   uint32_t tags = 0u;  // bit 2r (2r + 1): the thread's pair of round r has a low (high) run
   Cls cc;
+  // thread tid takes pairs pq + WG r with pq = 37 tid mod WG: neighbouring
+  // threads, whose items end up in neighbouring slots and lanes, then hold
+  // pairs of different rows, whose K overlap less (fewer same-address F_k
+  // atomics)
+  const int pq = (tid * 37) & (WG - 1);
   if (do_atm) {
-    for (int q = tid, r = 0; q < np; q += WG, ++r) {
+    for (int q = pq, r = 0; q < np; q += WG, ++r) {
       const int e = L.plist[q];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
@@ -709,7 +715,7 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
     for (uint32_t tg = tags; tg;) {  // only the pairs with a non-empty K
       const int r = __builtin_ctz(tg) >> 1;
       tg &= ~(3u << (2 * r));
-      const int e = L.plist[tid + WG * r];
+      const int e = L.plist[pq + WG * r];
       const int i = e & 127, j = e >> 7;
       const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
       u64 lo, hi;
