@@ -590,10 +590,13 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
   double e_lj = 0.0, w_lj = 0.0;
   long long n_pair = 0;
   int far = 0;  // a value beyond FAST_LIMIT: the block goes to the general path
-  // 3a. LJ over the owned pairs (contiguous chunk per thread, FP64)
+  // 3a. LJ over the owned pairs (contiguous chunk per thread, FP64; thread
+  //     tid takes chunk 37 tid mod WG, so that neighbouring lanes flush F_i of
+  //     different rows)
   if (do_lj) {
     const int mo = (no + WG - 1) / WG;
-    const int o0 = tid * mo < no ? tid * mo : no;
+    const int ch = (tid * 37) & (WG - 1);
+    const int o0 = ch * mo < no ? ch * mo : no;
     const int o1 = o0 + mo < no ? o0 + mo : no;
     int cur = -1;
     double fx = 0.0, fy = 0.0, fz = 0.0;
