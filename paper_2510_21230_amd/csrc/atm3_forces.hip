@@ -20,7 +20,7 @@
 //     pairs in FP64 (coordinates as FP32 value + residual);
 //  4. per pair the owned third molecules
 //     K(i,j) = mask_i & mask_j & allowed(code_i & code_j), all above j,
-//     as single-word work items of at most NCLS molecules each, placed in
+//     as single-word work items of at most NCLS (12) molecules each, placed in
 //     order of size by a block scan of per-thread class counts;
 //  5. ATM per triplet in FP32 (eq. atm and its gradient in squared sides,
 //     eq. forcepairs).  Each thread takes whole items in rounds, largest
@@ -378,8 +378,8 @@ __device__ __forceinline__ void add_fix_m(u64* ax, u64* ay, u64* az, int m, doub
 // popcount (class 1..NCLS); per-thread class counts are packed six 10-bit
 // fields to a word, which cannot overflow once the block's item total is
 // below 1024.
-constexpr int NCLS = 8;
-struct Cls {  // classes 1-6 in v0, 7-8 in v1
+constexpr int NCLS = 12;
+struct Cls {  // classes 1-6 in v0, 7-12 in v1
   u64 v0 = 0ull, v1 = 0ull;
   __device__ void add(int c, u64 d) {
     const int f = c - 1;
