@@ -175,8 +175,9 @@ def forward(params, D, pairs, disp, rc, bf16_ops=False):
     W1a, W1b = params["W1"][:NDESC], params["W1"][NDESC:]
     i, j = pairs[:, 0], pairs[:, 1]
     # x = [D_i + D_j, g(r_ij)]; in BF16 mode the descriptor sum is formed from
-    # the BF16 descriptors (exact in FP32) and rounded once more, and the
-    # biases enter the products as BF16 values
+    # the BF16 descriptors (exact in FP32) and rounded once more, the biases
+    # of the hidden layers enter the products as BF16 values, and the output
+    # layer takes BF16 h3 and W4 (b4 stays exact)
     dsum = _q(_q(D[i], q) + _q(D[j], q), q)
     z1 = dsum @ _q(W1a, q) + _q(g, q) @ _q(W1b, q) + _q(params["b1"], q)
     h1 = np.maximum(z1, 0.0)
@@ -184,7 +185,7 @@ def forward(params, D, pairs, disp, rc, bf16_ops=False):
     h2 = np.maximum(z2, 0.0)
     z3 = _q(h2, q) @ _q(params["W3"], q) + _q(params["b3"], q)
     h3 = np.maximum(z3, 0.0)
-    out = h3 @ params["W4"] + params["b4"]
+    out = _q(h3, q) @ _q(params["W4"], q) + params["b4"]
     s, t = out[:, 0], out[:, 1]
     F = np.zeros((n, 3))
     np.add.at(F, i, s[:, None] * u)

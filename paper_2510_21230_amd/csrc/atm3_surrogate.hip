@@ -40,6 +40,7 @@ static_assert(NPARAM == ATM3_MLP_NPARAM, "parameter layout");
 constexpr float R0 = 0.8f;
 constexpr int NPERM1 = 4 * 5 * 64 * 8;    // layer 1 A fragments: 4 descriptor K-steps + 1 radial (bf16)
 constexpr int NPERM = 4 * 4 * 2 * 64 * 8;  // layers 2, 3 A fragments (bf16)
+constexpr int NPERM4 = 4 * 2 * 64 * 8;     // output layer A fragments (2 of 32 rows used)
 constexpr int MAXSPLIT = 256;
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -472,7 +473,7 @@ __global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ X
 __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ P, bf16* __restrict__ w1b,
                                               bf16* __restrict__ w2b, bf16* __restrict__ w3b,
                                               bf16* __restrict__ wp1, bf16* __restrict__ wp2,
-                                              bf16* __restrict__ wp3) {
+                                              bf16* __restrict__ wp3, bf16* __restrict__ wp4) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < NIN * WID) w1b[idx] = (bf16)P[OFF_W1 + idx];
   if (idx < WID * WID) {
@@ -494,6 +495,14 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ P, bf16*
     wp2[idx] = (bf16)P[OFF_W2 + f * WID + out];
     wp3[idx] = (bf16)P[OFF_W3 + f * WID + out];
   }
+  if (idx < NPERM4) {
+    // [b][ks][lane][e]: W4[f][out] with f as for layers 2 and 3, rows
+    // out >= 2 zero
+    const int e = idx & 7, lane = (idx >> 3) & 63, ks = (idx >> 9) & 1, b = idx >> 10;
+    const int f = 32 * b + 16 * ks + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    const int out = lane & 31;
+    wp4[idx] = (bf16)(out < 2 ? P[OFF_W4 + 2 * f + out] : 0.f);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -506,6 +515,7 @@ struct PairArgs {
   const bf16* wp1;
   const bf16* wp2;
   const bf16* wp3;
+  const bf16* wp4;
   const float* P;
   int32_t np;
   float rc, w, inv_w, pi_rc;
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
   __shared__ bf16x8 w2s[32 * 64];
   __shared__ bf16x8 w3s[32 * 64];
   __shared__ float bsh[3 * WID];
-  __shared__ float w4s[2 * WID];
+  __shared__ bf16x8 w4f[4 * 2 * 64];
   const int tid = threadIdx.x;
   for (int q = tid; q < 4 * 5 * 64; q += 512) w1s[q] = ((const bf16x8*)a.wp1)[q];
   for (int q = tid; q < 32 * 64; q += 512) {
@@ -543,7 +553,7 @@ __global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
     bsh[WID + q] = a.P[OFF_B2 + q];
     bsh[2 * WID + q] = a.P[OFF_B3 + q];
   }
-  for (int q = tid; q < 2 * WID; q += 512) w4s[q] = a.P[OFF_W4 + q];
+  for (int q = tid; q < 4 * 2 * 64; q += 512) w4f[q] = ((const bf16x8*)a.wp4)[q];
   const float b40 = a.P[OFF_B4], b41 = a.P[OFF_B4 + 1];
   __syncthreads();
 
@@ -646,26 +656,31 @@ __global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
       }
     }
 
-    // output layer (FP32): s, t = W4^T relu(z3) + b4
-    float ps = 0.f, pt = 0.f;
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int f = 32 * ob + 8 * (r >> 2) + 4 * h + (r & 3);
-        const float v = relu(acc[ob][r]);
-        ps = fmaf(w4s[2 * f], v, ps);
-        pt = fmaf(w4s[2 * f + 1], v, pt);
-      }
-    if (DUMP && valid) {
+    // output layer on MFMA: rows 0 and 1 of W4^T relu(z3) are s and t (the
+    // other 30 rows of the A operand are zero); b4 is added in FP32
+    {
+      bf16x8 hb[4][2];
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dump4(a.h3 + (int64_t)p * WID + 32 * b + 8 * q + 4 * h, acc[b], 4 * q);
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)relu(acc[b][8 * ks + e]);
+      if (DUMP && valid) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dump4(a.h3 + (int64_t)p * WID + 32 * b + 8 * q + 4 * h, acc[b], 4 * q);
+      }
+      f32x16 c = zero16;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) c = mfma32(w4f[(b * 2 + ks) * 64 + lane], hb[b][ks], c);
+      // C row m = 8 (r / 4) + 4 h + r % 4: rows 0 and 1 sit in registers 0
+      // and 1 of the lanes with h = 0
+      if (h == 0 && valid) a.st[p] = make_float2(c[0] + b40, c[1] + b41);
     }
-    ps += __shfl_xor(ps, 32);
-    pt += __shfl_xor(pt, 32);
-    if (h == 0 && valid) a.st[p] = make_float2(ps + b40, pt + b41);
   }
 }
 
@@ -1055,6 +1070,7 @@ struct atm3_mlp {
   bf16* wp1 = nullptr;
   bf16* wp2 = nullptr;
   bf16* wp3 = nullptr;
+  bf16* wp4 = nullptr;
   double* dsum = nullptr;   // small device reduction outputs
   int64_t step = 0;
 };
@@ -1078,7 +1094,7 @@ double normal(uint64_t* s) {
 
 hipError_t prep_weights(atm3_ctx* ctx, atm3_mlp* m) {
   hipLaunchKernelGGL(k_prep, dim3(blocks_for(NPERM > NIN * WID ? NPERM : NIN * WID, 256)), dim3(256), 0,
-                     ctx->stream, m->params, m->w1b, m->w2b, m->w3b, m->wp1, m->wp2, m->wp3);
+                     ctx->stream, m->params, m->w1b, m->w2b, m->w3b, m->wp1, m->wp2, m->wp3, m->wp4);
   return hipGetLastError();
 }
 
@@ -1220,6 +1236,7 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   pa.wp1 = m->wp1;
   pa.wp2 = m->wp2;
   pa.wp3 = m->wp3;
+  pa.wp4 = m->wp4;
   pa.P = m->params;
   pa.np = (int32_t)G.np;
   pa.rc = (float)G.rc;
@@ -1513,7 +1530,8 @@ int atm3_mlp_create(atm3_ctx* ctx, uint64_t seed, atm3_mlp** out) {
             hipMalloc(&m->stats, 4 * 128) == hipSuccess && hipMalloc(&m->w1b, 2 * NIN * WID) == hipSuccess &&
             hipMalloc(&m->w2b, 2 * WID * WID) == hipSuccess && hipMalloc(&m->w3b, 2 * WID * WID) == hipSuccess &&
             hipMalloc(&m->wp1, 2 * NPERM1) == hipSuccess && hipMalloc(&m->wp2, 2 * NPERM) == hipSuccess &&
-            hipMalloc(&m->wp3, 2 * NPERM) == hipSuccess && hipMalloc(&m->dsum, 64) == hipSuccess;
+            hipMalloc(&m->wp3, 2 * NPERM) == hipSuccess && hipMalloc(&m->wp4, 2 * NPERM4) == hipSuccess &&
+            hipMalloc(&m->dsum, 64) == hipSuccess;
   if (!ok) {
     atm3_mlp_destroy(m);
     return fail(ctx, ATM3_ENOMEM, "device allocation for the model");
@@ -1545,7 +1563,8 @@ void atm3_mlp_destroy(atm3_mlp* m) {
   if (!m) return;
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  void* ps[] = {m->params, m->m, m->v, m->grad, m->stats, m->w1b, m->w2b, m->w3b, m->wp1, m->wp2, m->wp3, m->dsum};
+  void* ps[] = {m->params, m->m,   m->v,   m->grad, m->stats, m->w1b, m->w2b,
+                m->w3b,    m->wp1, m->wp2, m->wp3,  m->wp4,   m->dsum};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   delete m;
