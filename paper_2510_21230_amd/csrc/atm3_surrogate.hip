@@ -535,25 +535,31 @@ __device__ __forceinline__ void dump4(bf16* dst, const f32x16& v, int base_reg) 
   *(bf16x4*)dst = t;
 }
 
+// one workgroup per CU: 16 waves for inference, 8 when the activations are
+// dumped for training (more registers live)
 template <bool DUMP>
-__global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
+constexpr int pm_threads() { return DUMP ? 512 : 1024; }
+
+template <bool DUMP>
+__global__ __launch_bounds__(pm_threads<DUMP>()) void k_pair_mlp(PairArgs a) {
+  constexpr int PM_THREADS = pm_threads<DUMP>(), PM_WAVES = PM_THREADS / 64;
   __shared__ bf16x8 w1s[4 * 5 * 64];
   __shared__ bf16x8 w2s[32 * 64];
   __shared__ bf16x8 w3s[32 * 64];
   __shared__ float bsh[3 * WID];
   __shared__ bf16x8 w4f[4 * 2 * 64];
   const int tid = threadIdx.x;
-  for (int q = tid; q < 4 * 5 * 64; q += 512) w1s[q] = ((const bf16x8*)a.wp1)[q];
-  for (int q = tid; q < 32 * 64; q += 512) {
+  for (int q = tid; q < 4 * 5 * 64; q += PM_THREADS) w1s[q] = ((const bf16x8*)a.wp1)[q];
+  for (int q = tid; q < 32 * 64; q += PM_THREADS) {
     w2s[q] = ((const bf16x8*)a.wp2)[q];
     w3s[q] = ((const bf16x8*)a.wp3)[q];
   }
-  for (int q = tid; q < WID; q += 512) {
+  for (int q = tid; q < WID; q += PM_THREADS) {
     bsh[q] = a.P[OFF_B1 + q];
     bsh[WID + q] = a.P[OFF_B2 + q];
     bsh[2 * WID + q] = a.P[OFF_B3 + q];
   }
-  for (int q = tid; q < 4 * 2 * 64; q += 512) w4f[q] = ((const bf16x8*)a.wp4)[q];
+  for (int q = tid; q < 4 * 2 * 64; q += PM_THREADS) w4f[q] = ((const bf16x8*)a.wp4)[q];
   const float b40 = a.P[OFF_B4], b41 = a.P[OFF_B4 + 1];
   __syncthreads();
 
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(512) void k_pair_mlp(PairArgs a) {
   for (int e = 0; e < 8; ++e) ones[e] = (bf16)((e == 0 && h == 0) ? 1.f : 0.f);
   const f32x16 zero16 = {};
   const int ntiles = (a.np + 31) / 32;
-  for (int tile = blockIdx.x * 8 + wave; tile < ntiles; tile += gridDim.x * 8) {
+  for (int tile = blockIdx.x * PM_WAVES + wave; tile < ntiles; tile += gridDim.x * PM_WAVES) {
     // keeps the weight fragments in LDS: without it the loop-invariant LDS
     // reads are hoisted out of the tile loop into (spilled) registers
     asm volatile("" ::: "memory");
@@ -1254,9 +1260,9 @@ int sur_pairs_forward(atm3_ctx* ctx, atm3_mlp* m, const SurGeom& G, bool dump) {
   int64_t grid = dev_cu;  // one 8-wave workgroup per CU: one LDS copy of the weights
   if (grid * 8 > tiles) grid = (tiles + 7) / 8;
   if (dump)
-    hipLaunchKernelGGL(k_pair_mlp<true>, dim3((unsigned)grid), dim3(512), 0, ctx->stream, pa);
+    hipLaunchKernelGGL(k_pair_mlp<true>, dim3((unsigned)grid), dim3(pm_threads<true>()), 0, ctx->stream, pa);
   else
-    hipLaunchKernelGGL(k_pair_mlp<false>, dim3((unsigned)grid), dim3(512), 0, ctx->stream, pa);
+    hipLaunchKernelGGL(k_pair_mlp<false>, dim3((unsigned)grid), dim3(pm_threads<false>()), 0, ctx->stream, pa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "pair MLP launch");
   return ATM3_OK;
