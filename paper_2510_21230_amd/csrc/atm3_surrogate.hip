@@ -526,6 +526,25 @@ struct PairArgs {
   bf16* g16;  // [pair][16]
 };
 
+// BF16 of max(x, 0) for v[base .. base + 7]: round first, then one packed
+// 16-bit integer max per two values (a BF16 with the sign bit set, -0
+// included, is negative as an integer); the same bits as rounding the ReLU.
+__device__ __forceinline__ bf16x8 relu_bf16x8(const f32x16& v, int base) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef short s16x2 __attribute__((ext_vector_type(2)));
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 w;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x2 f = {v[base + 2 * q], v[base + 2 * q + 1]};
+    s16x2 t = __builtin_bit_cast(s16x2, __builtin_convertvector(f, bf16x2));
+    t = __builtin_elementwise_max(t, (s16x2)0);
+    w[q] = __builtin_bit_cast(uint32_t, t);
+  }
+  return __builtin_bit_cast(bf16x8, w);
+}
+
 __device__ __forceinline__ void dump4(bf16* dst, const f32x16& v, int base_reg) {
   // four consecutive features from registers base_reg .. base_reg+3 (after ReLU)
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -636,9 +655,7 @@ __global__ __launch_bounds__(pm_threads<DUMP>()) void k_pair_mlp(PairArgs a) {
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)relu(acc[b][8 * ks + e]);
+        for (int ks = 0; ks < 2; ++ks) hb[b][ks] = relu_bf16x8(acc[b], 8 * ks);
       bf16* dump = layer == 0 ? a.h1 : a.h2;
       if (DUMP && valid) {
 #pragma unroll
@@ -669,9 +686,7 @@ __global__ __launch_bounds__(pm_threads<DUMP>()) void k_pair_mlp(PairArgs a) {
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) hb[b][ks][e] = (bf16)relu(acc[b][8 * ks + e]);
+        for (int ks = 0; ks < 2; ++ks) hb[b][ks] = relu_bf16x8(acc[b], 8 * ks);
       if (DUMP && valid) {
 #pragma unroll
         for (int b = 0; b < 4; ++b)
