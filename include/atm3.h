@@ -278,6 +278,15 @@ int atm3_md_kick_drift(atm3_ctx* ctx, double* pos, double* vel, const float* for
 int atm3_md_kick(atm3_ctx* ctx, double* vel, const float* forces, int64_t n, double dt);
 int atm3_md_kinetic(atm3_ctx* ctx, const double* vel, int64_t n, double* ke_out);
 
+/* Isokinetic thermostat for the NVT runs of Sec. 5.1 (the paper does not name
+ * its thermostat): scales the device velocities `vel` (n*3 FP64, in place)
+ * so that sum v^2 / 2 = dof * temperature / 2, with dof degrees of freedom
+ * (3n - 3 for zero total momentum).  Velocities that are all zero are left
+ * as they are.  Only enqueues (kinetic energy reduced on the device).
+ * Errors: ATM3_EINVAL for a NULL pointer, n < 1, temperature <= 0 or not
+ * finite, dof outside [1, 3n]. */
+int atm3_md_rescale(atm3_ctx* ctx, double* vel, int64_t n, double temperature, int64_t dof);
+
 #ifdef __cplusplus
 }
 #endif

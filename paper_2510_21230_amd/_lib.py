@@ -33,7 +33,7 @@ EXPORTS = (
     "atm3_mlp_create", "atm3_mlp_destroy", "atm3_mlp_set_params", "atm3_mlp_get_params",
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
-    "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic",
+    "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale",
 )
 MLP_NPARAM = 43650
 MLP_NDESC = 64
@@ -136,6 +136,8 @@ def load():
         lib.atm3_md_kick.restype = ctypes.c_int
         lib.atm3_md_kinetic.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_double)]
         lib.atm3_md_kinetic.restype = ctypes.c_int
+        lib.atm3_md_rescale.argtypes = [vp, vp, i64, ctypes.c_double, i64]
+        lib.atm3_md_rescale.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -462,4 +464,44 @@ def md_run(pos, vel, box, steps, dt=0.002, record_every=1, frames=None, **force_
         ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
         if k % record_every == 0:
             record(k, r)
+    return out
+
+
+def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, **force_kw):
+    """Velocity Verlet with isokinetic rescaling to `temperature` after every
+    step (3N - 3 degrees of freedom), updating the FP64 device tensors `pos`
+    and `vel` in place; force_kw go to make_params.  Nothing synchronises with
+    the host inside the loop: each sampled step's result struct is written to
+    its own device row.  Returns a float64 array (n_samples, 4) with the
+    atm3_result fields e_lj, e_atm, w_lj, w_atm at steps sample_every,
+    2 sample_every, ..."""
+    import numpy as np
+    import torch
+    ctx = context(pos.device)
+    lib = ctx.lib
+    if not (vel.is_cuda and vel.dtype == torch.float64 and vel.shape == pos.shape and vel.is_contiguous()):
+        raise ValueError("vel must be a contiguous float64 tensor shaped like pos")
+    if not pos.is_contiguous():
+        raise ValueError("pos must be contiguous")
+    n = pos.shape[0]
+    prm = make_params(**force_kw)
+    f = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
+    stride = 128  # bytes per result row (>= sizeof(atm3_result), aligned)
+    ns = steps // sample_every
+    rows = torch.zeros((ns + 1) * stride, dtype=torch.uint8, device=pos.device)
+    ctx.compute_forces_async(pos, box, f, rows[ns * stride:], prm)  # spare row
+    for k in range(1, steps + 1):
+        ctx._check(lib.atm3_md_kick_drift(ctx.h, _ptr(pos), _ptr(vel), _ptr(f), n, float(dt)))
+        row = (k // sample_every - 1) if k % sample_every == 0 else ns
+        ctx.compute_forces_async(pos, box, f, rows[row * stride:], prm)
+        ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
+        ctx._check(lib.atm3_md_rescale(ctx.h, _ptr(vel), n, float(temperature), 3 * n - 3))
+    torch.cuda.synchronize(pos.device)
+    host = rows.cpu().numpy()
+    out = np.zeros((ns, 4))
+    for q in range(ns):
+        r = Result.from_buffer_copy(host[q * stride:q * stride + ctypes.sizeof(Result)].tobytes())
+        if r.status != 0:
+            raise Atm3Error(int(r.status), f"force evaluation of sample {q} returned status {int(r.status)}")
+        out[q] = (r.e_lj, r.e_atm, r.w_lj, r.w_atm)
     return out

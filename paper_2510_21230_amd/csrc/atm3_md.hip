@@ -1,7 +1,9 @@
 // Velocity Verlet (NVE) on FP64 positions and velocities with FP32 forces,
 // unit mass, reduced Lennard-Jones units (the MD runs of the paper's
 // validation, Sec. 5): half kick + drift, then after the force evaluation the
-// second half kick; kinetic energy by a fixed-order FP64 reduction.
+// second half kick; kinetic energy by a fixed-order FP64 reduction; an
+// isokinetic velocity rescaling for constant-temperature runs (Sec. 5.1 runs
+// NVT without naming its thermostat).
 #include <math.h>
 #include <string.h>
 
@@ -44,6 +46,15 @@ __global__ void k_ke_final(const double* __restrict__ part, int32_t np, double* 
   double s = 0.0;
   for (int b = 0; b < np; ++b) s += part[b];
   out[0] = 0.5 * s;
+}
+
+// v *= sqrt(ke_target / ke), ke from k_ke_final (left unchanged when ke is 0).
+__global__ __launch_bounds__(256) void k_rescale(double* __restrict__ v, int64_t m, const double* __restrict__ ke,
+                                                 double ke_target) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double k = ke[0];
+  if (k > 0.0) v[i] = v[i] * sqrt(ke_target / k);
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -102,6 +113,24 @@ int atm3_md_kinetic(atm3_ctx* ctx, const double* vel, int64_t n, double* ke_out)
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "kinetic energy");
   memcpy(ke_out, ctx->hres, 8);
+  return ATM3_OK;
+}
+
+int atm3_md_rescale(atm3_ctx* ctx, double* vel, int64_t n, double temperature, int64_t dof) {
+  int r = md_check(ctx, vel, vel, n, 1.0);
+  if (r) return r;
+  if (!(temperature > 0.0) || !isfinite(temperature)) return fail(ctx, ATM3_EINVAL, "temperature must be > 0");
+  if (dof < 1 || dof > 3 * n) return fail(ctx, ATM3_EINVAL, "dof must be in [1, 3n]");
+  const int64_t m = 3 * n;
+  const int np = (int)((m + KE_CHUNK - 1) / KE_CHUNK);
+  if ((r = ensure(ctx, B_SRED, 8 * (size_t)np + 64))) return r;
+  double* part = (double*)ctx->s.p[B_SRED];
+  hipLaunchKernelGGL(k_ke_part, dim3(np), dim3(256), 0, ctx->stream, vel, m, part + 1);
+  hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(64), 0, ctx->stream, part + 1, np, part);
+  hipLaunchKernelGGL(k_rescale, dim3(blocks_for(m, 256)), dim3(256), 0, ctx->stream, vel, m, (const double*)part,
+                     0.5 * (double)dof * temperature);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "rescale launch");
   return ATM3_OK;
 }
 

@@ -8,6 +8,8 @@ benchmark configurations of this package:
 * ``fcc``      -- FCC lattice filling a cubic periodic box at density rho,
                   ``n`` of its sites kept by a seeded permutation, each
                   coordinate jittered by U(-jitter, +jitter) sigma;
+* ``sc``       -- simple cubic lattice in a cubic box (single-phase start,
+                  Sec. 5.1);
 * ``uniform``  -- uniformly random molecules (the hit-rate study, Sec. 4);
 * ``slab``     -- vapour-liquid slab: FCC liquid layer + random-sequential-
                   addition vapour (uneven cell occupancy, Sec. 5.2);
@@ -48,6 +50,20 @@ def fcc(n: int, rho: float, jitter: float = 0.05, seed: int = SEED_BASE + 1):
         sites = sites[keep]
     pos = sites + rng.uniform(-jitter, jitter, size=sites.shape)
     return np.ascontiguousarray(pos), np.array([L, L, L])
+
+
+def sc(n: int, side: float, seed: int = SEED_BASE + 9):
+    """n molecules on a simple cubic lattice in a cubic box of the given side
+    (the single-phase start of Sec. 5.1): k = ceil(n^(1/3)) sites per side,
+    spacing side/k, n of the k^3 sites kept by a seeded permutation."""
+    rng = np.random.default_rng(seed)
+    k = int(math.ceil(n ** (1.0 / 3.0) - 1e-9))
+    g = (np.arange(k) + 0.5) * (side / k)
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    sites = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    if len(sites) > n:
+        sites = sites[np.sort(rng.permutation(len(sites))[:n])]
+    return np.ascontiguousarray(sites), np.array([side, side, side])
 
 
 def uniform(n: int, box, seed: int = SEED_BASE + 7):

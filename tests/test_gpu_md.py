@@ -73,3 +73,26 @@ def test_reversibility_and_momentum(torch_cuda):
     assert back < 1e-6
     assert mom < 1e-6 * len(pos)
     np.testing.assert_allclose(-v.cpu().numpy(), vel, atol=1e-5)
+
+
+def test_rescale_sets_kinetic_energy(torch_cuda):
+    """atm3_md_rescale: sum v^2/2 = dof T / 2 afterwards (FP64 host check),
+    directions unchanged; invalid temperature or dof are ATM3_EINVAL."""
+    torch = torch_cuda
+    import ctypes
+    import paper_2510_21230_amd as atm3
+    from paper_2510_21230_amd import _lib
+    n = 1000
+    vel = workloads.maxwell(n, 0.7, seed=workloads.SEED_BASE + 62)
+    v = torch.from_numpy(vel.copy()).cuda()
+    ctx = atm3.context(v.device)
+    _say(f"[md rescale] n={n}")
+    ctx._stream()
+    ctx._check(ctx.lib.atm3_md_rescale(ctx.h, _lib._ptr(v), n, 1.25, 3 * n - 3))
+    torch.cuda.synchronize()
+    got = v.cpu().numpy()
+    assert 0.5 * float((got * got).sum()) == pytest.approx(0.5 * (3 * n - 3) * 1.25, rel=1e-12)
+    lam = got / vel
+    assert np.allclose(lam, lam.flat[0], rtol=1e-12)
+    for T, dof in [(0.0, 3 * n - 3), (-1.0, 3), (float("nan"), 3), (1.0, 0), (1.0, 3 * n + 1)]:
+        assert ctx.lib.atm3_md_rescale(ctx.h, _lib._ptr(v), n, T, dof) == -1
