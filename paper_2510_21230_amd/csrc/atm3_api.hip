@@ -110,12 +110,11 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if (p->terms < 1 || p->terms > 3) return fail(ctx, ATM3_EINVAL, "terms must be a non-empty OR of ATM3_TERM_*");
   if (p->flags & ~ATM3_FLAG_CHECK_FINITE) return fail(ctx, ATM3_EINVAL, "unknown bits in flags");
   if (!make_grid(box, p->rc, g)) return fail(ctx, ATM3_EINVAL, "cell grid out of range (floor(L/rc) < 1 or too many cells)");
-  // cell offsets must equal minimum images for every visited set: 3 cells
-  // per dimension for the pairwise cutoff (5 for 3c18, whose base cell is
-  // chosen by lexicographic order of offsets spanning two steps), 5 for the
-  // product cutoff with 3c08, 7 with 3c18 or 3c01
-  int need = (p->variant == ATM3_VARIANT_3C18) ? 5 : 3;
-  if (p->truncation == ATM3_TRUNC_PRODUCT) need = (p->variant == ATM3_VARIANT_3C08) ? 5 : 7;
+  // 3 cells per dimension keep the 27 neighbours of a cell distinct; 3c18
+  // needs 5: its base cell is the lexicographically smallest of wrapped
+  // offsets spanning two steps, which for 3 or 4 cells depends on the
+  // labelling
+  const int need = (p->variant == ATM3_VARIANT_3C18) ? 5 : 3;
   for (int d = 0; d < 3; ++d)
     if (g->n[d] < need)
       return fail(ctx, ATM3_EINVAL,
@@ -277,7 +276,8 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
     e = launch_onesided(ctx, pos, n, g, *params, forces, out_dev);
   } else {
     e = launch_forces(ctx, pos, n, g, *params, forces, out_dev);
-    if (e == hipSuccess && params->variant != ATM3_VARIANT_3C08) e = launch_variant_counts(ctx, g, *params, out_dev);
+    if (e == hipSuccess && params->variant != ATM3_VARIANT_3C08)
+      e = launch_variant_counts(ctx, g, *params, out_dev, true);
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "force launch");
   return ATM3_OK;

@@ -132,11 +132,12 @@ size_t reduce_scratch_bytes();
 hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g,
                          const atm3_params& p, float* forces, atm3_result* res_dev);
 
-// Variants (atm3_variants.hip): candidate counts of the 3c18 / 3c01 cell sets
-// for the pairwise cutoff (patches n_candidates and, for 3c01, n_triplets of
-// the result the block kernels wrote), and the one-sided evaluation of the
-// product cutoff for every cell set.
-hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params& p, atm3_result* res_dev);
+// Variants (atm3_variants.hip): candidate counts of the cell sets from the
+// cell populations (patches n_candidates and, with `triple`, turns the block
+// kernels' 3c01 triplet count into the per-molecule one), and the one-sided
+// evaluation of the product cutoff for every cell set.
+hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params& p, atm3_result* res_dev,
+                                 bool triple);
 hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
                            float* forces, atm3_result* res_dev);
 

@@ -19,6 +19,8 @@
 // once per triplet (3c01: once per receiving molecule).
 #include <math.h>
 
+#include <algorithm>
+
 #include "atm3_internal.h"
 #include "atm3_terms.h"
 
@@ -54,7 +56,26 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a) {
   if (c < a.ncells) {
     const int cx = (int)(c % a.nx), cy = (int)((c / a.nx) % a.ny), cz = (int)(c / ((int64_t)a.nx * a.ny));
     const long long nb = a.start[c + 1] - a.start[c];
-    if (a.variant == ATM3_VARIANT_3C01) {
+    if (a.variant == ATM3_VARIANT_3C08) {
+      // base cell c: molecule triplets of its 2x2x2 block whose cells have
+      // c as componentwise minimum (corner codes AND to 0): eq.
+      // (celltriplet) for the cell itself, eq. (twoonetriplets) for the 13
+      // cell pairs, eq. (carttriplets) for the 44 cell triples
+      long long N[8];
+      for (int o = 0; o < 8; ++o) {
+        const int ux = wrapc(cx + (o & 1), a.nx), uy = wrapc(cy + ((o >> 1) & 1), a.ny), uz = wrapc(cz + (o >> 2), a.nz);
+        const int64_t cc = ((int64_t)uz * a.ny + uy) * a.nx + ux;
+        N[o] = a.start[cc + 1] - a.start[cc];
+      }
+      long long t = N[0] * (N[0] - 1) * (N[0] - 2) / 6;
+      for (int p = 0; p < 8; ++p)
+        for (int q = p + 1; q < 8; ++q) {
+          if ((p & q) == 0) t += N[q] * (N[p] * (N[p] - 1) / 2) + N[p] * (N[q] * (N[q] - 1) / 2);
+          for (int r = q + 1; r < 8; ++r)
+            if ((p & q & r) == 0) t += N[p] * N[q] * N[r];
+        }
+      v = (unsigned long long)t;
+    } else if (a.variant == ATM3_VARIANT_3C01) {
       // every molecule of cell c: pairs of the other molecules of its 27 cells
       long long s = 0;
       for (int q = 0; q < 27; ++q) {
@@ -87,33 +108,41 @@ __global__ __launch_bounds__(256) void k_cand(CandArgs a) {
   if (threadIdx.x == 0) a.part[blockIdx.x] = ((ws[0] + ws[1]) + ws[2]) + ws[3];
 }
 
+// n_candidates of the result; with `triple`, a 3c01 triplet count made by
+// the block kernel (each triplet once) becomes the 3c01 count (once per
+// receiving molecule).
 __global__ void k_cand_final(const unsigned long long* __restrict__ part, int32_t np, int32_t variant,
-                             atm3_result* __restrict__ res) {
+                             int32_t triple, atm3_result* __restrict__ res) {
   if (threadIdx.x != 0) return;
   unsigned long long s = 0;
   for (int b = 0; b < np; ++b) s += part[b];
   res->n_candidates = (int64_t)s;
-  if (variant == ATM3_VARIANT_3C01) res->n_triplets *= 3;
+  if (triple && variant == ATM3_VARIANT_3C01) res->n_triplets *= 3;
 }
 
 // ---------------------------------------------------------------------------
 // one-sided evaluation under the product cutoff
 // ---------------------------------------------------------------------------
-constexpr int CAND_CAP = 2048;  // candidates per molecule (LDS, per wave)
-constexpr int OS_WAVES = 2;
+constexpr int CAND_CAP = 2048;  // candidates per cell neighbourhood (LDS)
+constexpr int OS_WAVES = 8;     // waves per block
+constexpr int OS_SPLIT = 2;     // waves per molecule (rows xa split by parity)
+constexpr int OS_MOLS = OS_WAVES / OS_SPLIT;  // molecules per group
+constexpr int OS_QCAP = 128;    // per-wave queue of pairs that passed the FP32 test
+constexpr int OS_MAXNB = 125;   // neighbour cells (reach 2)
 
 struct OneArgs {
   const double4* sorted;
   const int32_t* start;
-  const int32_t* cell_of;
   const double* pos;
-  int32_t n, nx, ny, nz, reach, variant, terms;
+  int32_t nx, ny, nz, reach, variant, terms, groups;
   double side[3], box[3];
-  double rc2, rc6, sig2, eps4, eps24, nu;
+  double rc2, rc6, sig2, eps4, eps24;
+  float boxf[3], invf[3];
+  float rc2hi, lo6f, hi6f, small2;  // FP32 thresholds of the exact decisions
   float k3nu, k15nu, k075nu;
   float* forces;
-  double* dpart;              // per block: e_lj, w_lj, e_atm, w_atm
-  unsigned long long* ipart;  // per block: n_pairs, n_triplets, n_candidates, overflow
+  double* dpart;              // per block: e_lj, w_lj, e_atm, unused
+  unsigned long long* ipart;  // per block: n_pairs, n_triplets, unused, overflow
 };
 
 // Truncation test of the oracle: squared sides sorted ascending, multiplied
@@ -131,6 +160,10 @@ struct Off {
   int x, y, z;
 };
 
+__device__ __forceinline__ Off unpack_off(uint32_t u) {
+  return Off{(int)(u & 255u) - 8, (int)((u >> 8) & 255u) - 8, (int)((u >> 16) & 255u) - 8};
+}
+
 __device__ __forceinline__ bool lex_less(const Off& p, const Off& q) {
   if (p.z != q.z) return p.z < q.z;
   if (p.y != q.y) return p.y < q.y;
@@ -141,15 +174,20 @@ __device__ __forceinline__ Off rel(const Off& a, const Off& b, int nx, int ny, i
   return Off{wrap_off(a.x - b.x, nx), wrap_off(a.y - b.y, ny), wrap_off(a.z - b.z, nz)};
 }
 
+__device__ __forceinline__ bool near1(const Off& a, const Off& b) {
+  const int dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+  return dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+}
+
 __device__ __forceinline__ bool adjacent(const Off& a, const Off& b, int nx, int ny, int nz) {
-  const Off r = rel(b, a, nx, ny, nz);
-  return r.x >= -1 && r.x <= 1 && r.y >= -1 && r.y <= 1 && r.z >= -1 && r.z <= 1;
+  return near1(rel(b, a, nx, ny, nz), Off{0, 0, 0});
 }
 
 // Visited test of the triplet labelled t0 < t1 < t2 (by input index) with
 // cell offsets o0, o1, o2 (relative to any common cell); for 3c01 returns the
 // receiving mask (bit q: molecule t_q takes its share), else 7 or 0.
-__device__ int visited_mask(int variant, const Off& o0, const Off& o1, const Off& o2, int nx, int ny, int nz) {
+__device__ __forceinline__ int visited_mask(int variant, const Off& o0, const Off& o1, const Off& o2, int nx, int ny,
+                                            int nz) {
   if (variant == ATM3_VARIANT_3C01) {
     const bool a01 = adjacent(o0, o1, nx, ny, nz), a02 = adjacent(o0, o2, nx, ny, nz),
                a12 = adjacent(o1, o2, nx, ny, nz);
@@ -165,144 +203,255 @@ __device__ int visited_mask(int variant, const Off& o0, const Off& o1, const Off
   }
   // 3c18: lexicographically smallest cell as base; the others within one
   // step of it in every dimension
-  const Off* o[3] = {&z0, &r1, &r2};
-  int m = 0;
-  if (lex_less(r1, *o[m])) m = 1;
-  if (lex_less(r2, *o[m])) m = 2;
-  for (int t = 0; t < 3; ++t) {
-    if (t == m) continue;
-    const int dx = o[t]->x - o[m]->x, dy = o[t]->y - o[m]->y, dz = o[t]->z - o[m]->z;
-    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return 0;
-  }
-  return 7;
+  Off b = z0;
+  if (lex_less(r1, b)) b = r1;
+  if (lex_less(r2, b)) b = r2;
+  return (near1(z0, b) && near1(r1, b) && near1(r2, b)) ? 7 : 0;
+}
+
+// Minimum image of an FP32 displacement (for the FP32 pre-test and the force
+// arithmetic; every decision is taken again in FP64 near its boundary).
+__device__ __forceinline__ float3 wrapf(float3 d, const float* L, const float* inv) {
+  d.x = fmaf(-L[0], rintf(d.x * inv[0]), d.x);
+  d.y = fmaf(-L[1], rintf(d.y * inv[1]), d.y);
+  d.z = fmaf(-L[2], rintf(d.z * inv[2]), d.z);
+  return d;
+}
+
+__device__ __forceinline__ float sq3(float3 d) { return fmaf(d.z, d.z, fmaf(d.y, d.y, d.x * d.x)); }
+
+// Energy term of eq. (atm) and the force on molecule i of the triplet (i, j,
+// k) from r_ij = -va, r_ik = -vb and the squared sides x = |r_ij|^2,
+// y = |r_ik|^2, z = |r_jk|^2 (eq. forcepairs: F_i = c_x r_ij + c_y r_ik).
+__device__ __forceinline__ float atm_on_i(float3 va, float3 vb, float x, float y, float z, float k3nu, float k15nu,
+                                          float k075nu, float3* f) {
+  const float s = x + y + z;
+  const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
+  const float AB = A * B, AC = A * C, BC = B * C;
+  const float P = AB * C;
+  const float S = AB + AC + BC;
+  const float Q = (x * y) * z;
+  const float t1 = __builtin_amdgcn_rsqf(Q);
+  const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
+  const float G = fmaf(k15nu * P, t5, k3nu * t3);
+  const float H = k075nu * t5;
+  const float cx = fmaf(G, (y * z) * t2, -H * fmaf(-2.f, BC, S));
+  const float cy = fmaf(G, (x * z) * t2, -H * fmaf(-2.f, AC, S));
+  f->x = -fmaf(cx, va.x, cy * vb.x);
+  f->y = -fmaf(cx, va.y, cy * vb.y);
+  f->z = -fmaf(cx, va.z, cy * vb.z);
+  return fmaf(0.375f * P, t5, t3);
 }
 
 struct OneLds {
-  int32_t orig[OS_WAVES][CAND_CAP];
-  int8_t off[OS_WAVES][CAND_CAP][4];
-  float4 v[OS_WAVES][CAND_CAP];      // r_j - r_m (FP32), .w unused
-  double x[OS_WAVES][CAND_CAP];      // exact squared distance to m
-  double red[OS_WAVES][4];
-  unsigned long long redi[OS_WAVES][4];
+  float4 p[CAND_CAP];         // candidate position relative to the centre cell's centre; .w = input index
+  uint32_t off[CAND_CAP];     // packed cell offset (dx+8) | (dy+8) << 8 | (dz+8) << 16
+  uint32_t q[OS_WAVES][OS_QCAP];  // queued pairs xa | xb << 16
+  int32_t cnt[OS_MAXNB + 3], base[OS_MAXNB + 3];
+  int32_t cell[OS_MAXNB + 3];
+  double facc[OS_WAVES][3];
+  double red[OS_WAVES][3];
+  unsigned long long redi[OS_WAVES][2];
+  int32_t nc;
 };
 
+// One block per (cell, group slice): the candidates of the cell's
+// neighbourhood are staged once in LDS and shared by every molecule of the
+// cell; each molecule is handled by OS_SPLIT waves (candidate rows split by
+// parity), each lane taking the partners xb > xa of row xa.  Pairs that pass
+// the FP32 product test with a relative guard band are queued and evaluated
+// 64 at a time; pairs inside the band take the oracle's FP64 decision.  WV:
+// molecule-candidate vectors need a minimum-image wrap (fewer than
+// 2 (reach + 1) cells per dimension); WJ: candidate-candidate vectors do
+// (fewer than 4 (reach + 1)).
+template <bool WV, bool WJ>
 __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   __shared__ OneLds L;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t c = blockIdx.x / a.groups;
+  const int g = blockIdx.x % a.groups;
+  const int cx = (int)(c % a.nx), cy = (int)((c / a.nx) % a.ny), cz = (int)(c / ((int64_t)a.nx * a.ny));
+  const int R = a.reach, span = 2 * R + 1, nnb = span * span * span, q0 = (nnb - 1) / 2;
   double e_lj = 0.0, w_lj = 0.0, e3 = 0.0;
-  unsigned long long npair = 0, ntrip = 0, ncand = 0, over = 0;
-  const int s = blockIdx.x * OS_WAVES + w;
-  if (s < a.n) {
-    const double4 me = a.sorted[s];
-    const int om = (int)me.w;
-    const int c = a.cell_of[om];
-    const int cx = c % a.nx, cy = (c / a.nx) % a.ny, cz = c / (a.nx * a.ny);
-    // candidates: molecules of the cells within `reach` of m's cell
-    int nc = 0;
-    const int R = a.reach, span = 2 * R + 1;
-    for (int q = 0; q < span * span * span; ++q) {
+  unsigned long long npair = 0, ntrip = 0, over = 0;
+  // neighbour cells (dx fastest) and their populations
+  if (threadIdx.x < nnb) {
+    const int q = threadIdx.x;
+    const int dx = q % span - R, dy = (q / span) % span - R, dz = q / (span * span) - R;
+    const int ux = wrapc(cx + dx, a.nx), uy = wrapc(cy + dy, a.ny), uz = wrapc(cz + dz, a.nz);
+    const int cc = (uz * a.ny + uy) * a.nx + ux;
+    L.cell[q] = cc;
+    L.cnt[q] = a.start[cc + 1] - a.start[cc];
+  }
+  __syncthreads();
+  if (w == 0) {
+    int run = 0;
+    for (int b0 = 0; b0 < nnb; b0 += 64) {
+      const int q = b0 + lane;
+      const int v = q < nnb ? L.cnt[q] : 0;
+      int incl = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+      }
+      if (q < nnb) L.base[q] = run + incl - v;
+      run += __shfl(incl, 63);
+    }
+    if (lane == 0) L.nc = run;
+  }
+  __syncthreads();
+  const int nc = L.nc;
+  if (nc > CAND_CAP) {
+    over = 1;
+  } else {
+    for (int q = w; q < nnb; q += OS_WAVES) {
       const int dx = q % span - R, dy = (q / span) % span - R, dz = q / (span * span) - R;
-      const int ux = wrapc(cx + dx, a.nx), uy = wrapc(cy + dy, a.ny), uz = wrapc(cz + dz, a.nz);
-      const int cc = (uz * a.ny + uy) * a.nx + ux;
-      const int t0 = a.start[cc], t1 = a.start[cc + 1];
-      for (int b = t0; b < t1; b += 64) {
-        const int t = b + lane;
-        const bool ok = t < t1 && t != s;
-        const unsigned long long bits = __ballot(ok);
-        const int slot = nc + __popcll(bits & ((1ull << lane) - 1ull));
-        if (ok && slot < CAND_CAP) {
-          const double4 o = a.sorted[t];
-          const int oj = (int)o.w;
-          L.orig[w][slot] = oj;
-          L.off[w][slot][0] = (int8_t)dx;
-          L.off[w][slot][1] = (int8_t)dy;
-          L.off[w][slot][2] = (int8_t)dz;
-          // r_j - r_m = loc_j - loc_m + offset of j's cell
-          const double ex = (o.x - me.x) + dx * a.side[0], ey = (o.y - me.y) + dy * a.side[1],
-                       ez = (o.z - me.z) + dz * a.side[2];
-          L.v[w][slot] = make_float4((float)ex, (float)ey, (float)ez, 0.f);
-          L.x[w][slot] = exact_r2(a.pos, om, oj, a.box[0], a.box[1], a.box[2]);
-        }
-        nc += __popcll(bits);
+      const int t0 = a.start[L.cell[q]], m = L.cnt[q], b = L.base[q];
+      const uint32_t ou = (uint32_t)(dx + 8) | ((uint32_t)(dy + 8) << 8) | ((uint32_t)(dz + 8) << 16);
+      for (int t = lane; t < m; t += 64) {
+        const double4 o = a.sorted[t0 + t];
+        L.p[b + t] = make_float4((float)(o.x + dx * a.side[0]), (float)(o.y + dy * a.side[1]),
+                                 (float)(o.z + dz * a.side[2]), __int_as_float((int)o.w));
+        L.off[b + t] = ou;
       }
-    }
-    if (nc > CAND_CAP) {
-      over = 1;
-      nc = CAND_CAP;
-    }
-    __builtin_amdgcn_wave_barrier();
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    // Lennard-Jones pairs containing m (FP64)
-    if (a.terms & ATM3_TERM_LJ) {
-      for (int q = lane; q < nc; q += 64) {
-        const double x = L.x[w][q];
-        if (!(x < a.rc2)) continue;
-        const float4 vj = L.v[w][q];
-        const double s2 = a.sig2 / x, s6 = s2 * s2 * s2, s12 = s6 * s6;
-        const double f = a.eps24 * (2.0 * s12 - s6) / x;  // F_m = f (r_m - r_j)
-        fx -= f * (double)vj.x;
-        fy -= f * (double)vj.y;
-        fz -= f * (double)vj.z;
-        e_lj += 0.5 * a.eps4 * (s12 - s6);
-        w_lj += 0.5 * f * x;
-        npair += (om < L.orig[w][q]) ? 1 : 0;
-      }
-    }
-    // ATM triplets containing m
-    if (a.terms & ATM3_TERM_ATM) {
-      const Off om_off{0, 0, 0};
-      const float4 pm = make_float4(0.f, 0.f, 0.f, 0.f);
-      const long long T = (long long)nc * (nc - 1) / 2;
-      for (long long q = lane; q < T; q += 64) {
-        int xa = (int)((2.0 * nc - 1.0 - sqrt((2.0 * nc - 1.0) * (2.0 * nc - 1.0) - 8.0 * (double)q)) * 0.5);
-        if (xa < 0) xa = 0;
-        while (xa > 0 && (long long)xa * (2 * nc - xa - 1) / 2 > q) --xa;
-        while ((long long)(xa + 1) * (2 * nc - xa - 2) / 2 <= q) ++xa;
-        const int xb = (int)(q - (long long)xa * (2 * nc - xa - 1) / 2) + xa + 1;
-        const int oj = L.orig[w][xa], ok = L.orig[w][xb];
-        const Off fj{L.off[w][xa][0], L.off[w][xa][1], L.off[w][xa][2]};
-        const Off fk{L.off[w][xb][0], L.off[w][xb][1], L.off[w][xb][2]};
-        // label by input index: t0 < t1 < t2
-        int id[3] = {om, oj, ok};
-        Off of[3] = {om_off, fj, fk};
-        int me_pos = 0;
-        if (id[1] < id[0]) { int ti = id[0]; id[0] = id[1]; id[1] = ti; Off to = of[0]; of[0] = of[1]; of[1] = to; }
-        if (id[2] < id[1]) { int ti = id[1]; id[1] = id[2]; id[2] = ti; Off to = of[1]; of[1] = of[2]; of[2] = to; }
-        if (id[1] < id[0]) { int ti = id[0]; id[0] = id[1]; id[1] = ti; Off to = of[0]; of[0] = of[1]; of[1] = to; }
-        me_pos = (id[0] == om) ? 0 : (id[1] == om ? 1 : 2);
-        const int vm = visited_mask(a.variant, of[0], of[1], of[2], a.nx, a.ny, a.nz);
-        const bool mine = (vm >> me_pos) & 1;
-        if (a.variant == ATM3_VARIANT_3C01) ncand += mine ? 1 : 0;
-        else ncand += (vm && me_pos == 0) ? 1 : 0;
-        if (!mine) continue;
-        const double z = exact_r2(a.pos, oj, ok, a.box[0], a.box[1], a.box[2]);
-        if (!product_ok(L.x[w][xa], L.x[w][xb], z, a.rc6)) continue;
-        const Trip r = atm_triplet(pm, L.v[w][xa], L.v[w][xb], a.k3nu, a.k15nu, a.k075nu);
-        fx += (double)r.fix;
-        fy += (double)r.fiy;
-        fz += (double)r.fiz;
-        e3 += (double)r.eu;
-        if (a.variant == ATM3_VARIANT_3C01 || me_pos == 0) ++ntrip;
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      fx += __shfl_xor(fx, off);
-      fy += __shfl_xor(fy, off);
-      fz += __shfl_xor(fz, off);
-    }
-    if (lane == 0) {
-      a.forces[3 * (int64_t)om + 0] = (float)fx;
-      a.forces[3 * (int64_t)om + 1] = (float)fy;
-      a.forces[3 * (int64_t)om + 2] = (float)fz;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    e_lj += __shfl_xor(e_lj, off);
-    w_lj += __shfl_xor(w_lj, off);
-    e3 += __shfl_xor(e3, off);
-    npair += __shfl_xor(npair, off);
-    ntrip += __shfl_xor(ntrip, off);
-    ncand += __shfl_xor(ncand, off);
+  __syncthreads();
+  const int pop = L.cnt[q0];
+  if (!over) {
+    for (int gg = g; gg * OS_MOLS < pop; gg += a.groups) {
+      const int ml = gg * OS_MOLS + w / OS_SPLIT, h = w % OS_SPLIT;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      if (ml < pop) {
+        const int self = L.base[q0] + ml;
+        const float4 pm4 = L.p[self];
+        const float3 pm = make_float3(pm4.x, pm4.y, pm4.z);
+        const int om = __float_as_int(pm4.w);
+        auto vec = [&](const float4 p) {
+          float3 d = make_float3(p.x - pm.x, p.y - pm.y, p.z - pm.z);
+          if (WV) d = wrapf(d, a.boxf, a.invf);
+          return d;
+        };
+        // Lennard-Jones pairs containing m (FP64 on the exact squared distance)
+        if (a.terms & ATM3_TERM_LJ) {
+          for (int q = lane + 64 * h; q < nc; q += 64 * OS_SPLIT) {
+            const float4 pj = L.p[q];
+            const float3 v = vec(pj);
+            if (q == self || !(sq3(v) < a.rc2hi)) continue;
+            const int oj = __float_as_int(pj.w);
+            const double x = exact_r2(a.pos, om, oj, a.box[0], a.box[1], a.box[2]);
+            if (!(x < a.rc2)) continue;
+            const double s2 = a.sig2 / x, s6 = s2 * s2 * s2, s12 = s6 * s6;
+            const double f = a.eps24 * (2.0 * s12 - s6) / x;  // F_m = f (r_m - r_j)
+            fx -= f * (double)v.x;
+            fy -= f * (double)v.y;
+            fz -= f * (double)v.z;
+            e_lj += 0.5 * a.eps4 * (s12 - s6);
+            w_lj += 0.5 * f * x;
+            npair += (om < oj) ? 1 : 0;
+          }
+        }
+        if (a.terms & ATM3_TERM_ATM) {
+          uint32_t* qb = L.q[w];
+          int qn = 0;
+          // evaluate the queued pairs [qn - cnt, qn), one per lane
+          auto drain = [&](int cnt) {
+            if (lane < cnt) {
+              const uint32_t e = qb[qn - cnt + lane];
+              const int xa = (int)(e & 0xffffu), xb = (int)(e >> 16);
+              const float4 pa = L.p[xa], pb = L.p[xb];
+              const float3 va = vec(pa), vb = vec(pb);
+              float3 jk = make_float3(vb.x - va.x, vb.y - va.y, vb.z - va.z);
+              if (WJ) jk = wrapf(jk, a.boxf, a.invf);
+              const float x = sq3(va), y = sq3(vb), z = sq3(jk);
+              const float pf = (x * y) * z;
+              const int oa = __float_as_int(pa.w), ob = __float_as_int(pb.w);
+              bool in = true;
+              if (!(pf < a.lo6f) || fminf(x, fminf(y, z)) < a.small2)
+                in = product_ok(exact_r2(a.pos, om, oa, a.box[0], a.box[1], a.box[2]),
+                                exact_r2(a.pos, om, ob, a.box[0], a.box[1], a.box[2]),
+                                exact_r2(a.pos, oa, ob, a.box[0], a.box[1], a.box[2]), a.rc6);
+              if (in) {
+                // label by input index: t0 < t1 < t2
+                const Off z0{0, 0, 0}, fa = unpack_off(L.off[xa]), fb = unpack_off(L.off[xb]);
+                int i0 = om, i1 = oa, i2 = ob;
+                Off o0 = z0, o1 = fa, o2 = fb, to;
+                int ti;
+                if (i1 < i0) { ti = i0; i0 = i1; i1 = ti; to = o0; o0 = o1; o1 = to; }
+                if (i2 < i1) { ti = i1; i1 = i2; i2 = ti; to = o1; o1 = o2; o2 = to; }
+                if (i1 < i0) { ti = i0; i0 = i1; i1 = ti; to = o0; o0 = o1; o1 = to; }
+                const int me = (om > oa ? 1 : 0) + (om > ob ? 1 : 0);
+                const int vm = visited_mask(a.variant, o0, o1, o2, a.nx, a.ny, a.nz);
+                if ((vm >> me) & 1) {
+                  float3 f;
+                  const float eu = atm_on_i(va, vb, x, y, z, a.k3nu, a.k15nu, a.k075nu, &f);
+                  fx += (double)f.x;
+                  fy += (double)f.y;
+                  fz += (double)f.z;
+                  e3 += (double)eu;
+                  if (a.variant == ATM3_VARIANT_3C01 || me == 0) ++ntrip;
+                }
+              }
+            }
+            qn -= cnt;
+          };
+          for (int xa = h; xa + 1 < nc; xa += OS_SPLIT) {
+            if (xa == self) continue;
+            const float3 va = vec(L.p[xa]);
+            const float xa2 = sq3(va);
+            for (int xb0 = xa + 1; xb0 < nc; xb0 += 64) {
+              const int xb = xb0 + lane;
+              bool acc = false;
+              if (xb < nc && xb != self) {
+                const float3 vb = vec(L.p[xb]);
+                float3 jk = make_float3(vb.x - va.x, vb.y - va.y, vb.z - va.z);
+                if (WJ) jk = wrapf(jk, a.boxf, a.invf);
+                const float y = sq3(vb), z = sq3(jk);
+                acc = (xa2 * y) * z < a.hi6f || fminf(xa2, fminf(y, z)) < a.small2;
+              }
+              const unsigned long long bits = __ballot(acc);
+              if (acc) qb[qn + __popcll(bits & ((1ull << lane) - 1ull))] = (uint32_t)xa | ((uint32_t)xb << 16);
+              qn += __popcll(bits);
+              __builtin_amdgcn_wave_barrier();
+              if (qn >= 64) {
+                drain(64);
+                __builtin_amdgcn_wave_barrier();
+              }
+            }
+          }
+          if (qn > 0) drain(qn);
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        fx += __shfl_xor(fx, o);
+        fy += __shfl_xor(fy, o);
+        fz += __shfl_xor(fz, o);
+      }
+      if (lane == 0) {
+        L.facc[w][0] = fx;
+        L.facc[w][1] = fy;
+        L.facc[w][2] = fz;
+      }
+      __syncthreads();
+      if (threadIdx.x < OS_MOLS) {
+        const int m2 = gg * OS_MOLS + threadIdx.x;
+        if (m2 < pop) {
+          const int om = __float_as_int(L.p[L.base[q0] + m2].w);
+          double s[3] = {0.0, 0.0, 0.0};
+          for (int hh = 0; hh < OS_SPLIT; ++hh)
+            for (int d = 0; d < 3; ++d) s[d] += L.facc[threadIdx.x * OS_SPLIT + hh][d];
+          for (int d = 0; d < 3; ++d) a.forces[3 * (int64_t)om + d] = (float)s[d];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    e_lj += __shfl_xor(e_lj, o);
+    w_lj += __shfl_xor(w_lj, o);
+    e3 += __shfl_xor(e3, o);
+    npair += __shfl_xor(npair, o);
+    ntrip += __shfl_xor(ntrip, o);
   }
   if (lane == 0) {
     L.red[w][0] = e_lj;
@@ -310,8 +459,6 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
     L.red[w][2] = e3;
     L.redi[w][0] = npair;
     L.redi[w][1] = ntrip;
-    L.redi[w][2] = ncand;
-    L.redi[w][3] = over;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -320,11 +467,16 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
       for (int q = 0; q < OS_WAVES; ++q) sum += L.red[q][k];
       a.dpart[4 * (int64_t)blockIdx.x + k] = sum;
     }
-    for (int k = 0; k < 4; ++k) {
-      unsigned long long sum = 0;
-      for (int q = 0; q < OS_WAVES; ++q) sum += L.redi[q][k];
-      a.ipart[4 * (int64_t)blockIdx.x + k] = sum;
+    a.dpart[4 * (int64_t)blockIdx.x + 3] = 0.0;
+    unsigned long long s0 = 0, s1 = 0;
+    for (int q = 0; q < OS_WAVES; ++q) {
+      s0 += L.redi[q][0];
+      s1 += L.redi[q][1];
     }
+    a.ipart[4 * (int64_t)blockIdx.x + 0] = s0;
+    a.ipart[4 * (int64_t)blockIdx.x + 1] = s1;
+    a.ipart[4 * (int64_t)blockIdx.x + 2] = 0;
+    a.ipart[4 * (int64_t)blockIdx.x + 3] = over;
   }
 }
 
@@ -374,7 +526,8 @@ __global__ __launch_bounds__(256) void k_onesided_final(const double* __restrict
 
 }  // namespace
 
-hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params& p, atm3_result* res_dev) {
+hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params& p, atm3_result* res_dev,
+                                 bool triple) {
   const unsigned nb = blocks_for(g.ncells, 256);
   if (ensure(ctx, B_SRED, 8 * (size_t)nb + 64)) return hipErrorOutOfMemory;
   CandArgs a;
@@ -386,36 +539,58 @@ hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params
   a.variant = p.variant;
   a.part = (unsigned long long*)ctx->s.p[B_SRED];
   hipLaunchKernelGGL(k_cand, dim3(nb), dim3(256), 0, ctx->stream, a);
-  hipLaunchKernelGGL(k_cand_final, dim3(1), dim3(64), 0, ctx->stream, a.part, (int32_t)nb, p.variant, res_dev);
+  hipLaunchKernelGGL(k_cand_final, dim3(1), dim3(64), 0, ctx->stream, a.part, (int32_t)nb, p.variant,
+                     triple ? 1 : 0, res_dev);
   return hipGetLastError();
 }
 
 hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
                            float* forces, atm3_result* res_dev) {
-  const unsigned nb = blocks_for(n, OS_WAVES);
-  if (ensure(ctx, B_SRED, 64 * (size_t)nb + 64)) return hipErrorOutOfMemory;
+  const int reach = (p.variant == ATM3_VARIANT_3C18) ? 2 : 1;
+  // group slices per cell: about one group of OS_MOLS molecules per block
+  const int64_t per_cell = (n + g.ncells - 1) / g.ncells;
+  const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
+  const int64_t nb64 = g.ncells * groups;
+  if (nb64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)nb64;
+  // room for the per-block partials and, afterwards, the candidate partials
+  // of launch_variant_counts (so that its ensure does not reallocate)
+  const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
+  if (ensure(ctx, B_SRED, need > need_c ? need : need_c)) return hipErrorOutOfMemory;
   OneArgs a;
   a.sorted = (const double4*)ctx->s.p[B_SORTED];
   a.start = (const int32_t*)ctx->s.p[B_START];
-  a.cell_of = (const int32_t*)ctx->s.p[B_CELL_OF];
   a.pos = pos;
-  a.n = (int32_t)n;
   a.nx = g.n[0];
   a.ny = g.n[1];
   a.nz = g.n[2];
-  a.reach = (p.variant == ATM3_VARIANT_3C18) ? 2 : 1;
+  a.reach = reach;
   a.variant = p.variant;
   a.terms = p.terms;
+  a.groups = groups;
+  double smin = g.side[0];
+  bool wv = false, wj = false;
   for (int d = 0; d < 3; ++d) {
     a.side[d] = g.side[d];
     a.box[d] = g.box[d];
+    a.boxf[d] = (float)g.box[d];
+    a.invf[d] = (float)(1.0 / g.box[d]);
+    smin = std::min(smin, g.side[d]);
+    wv = wv || g.n[d] < 2 * (reach + 1);
+    wj = wj || g.n[d] < 4 * (reach + 1);
   }
   a.rc2 = p.rc * p.rc;
   a.rc6 = (a.rc2 * a.rc2) * a.rc2;
+  // FP32 pre-tests: a relative band of 1e-4 around each boundary, and every
+  // side shorter than a quarter cell, go to the exact FP64 decision (the
+  // FP32 squared sides err by less than 3e-5 relative outside that range)
+  a.rc2hi = (float)(a.rc2 * (1.0 + 1e-4));
+  a.lo6f = (float)(a.rc6 * (1.0 - 1e-4));
+  a.hi6f = (float)(a.rc6 * (1.0 + 1e-4));
+  a.small2 = (float)(0.0625 * smin * smin);
   a.sig2 = p.sigma * p.sigma;
   a.eps4 = 4.0 * p.eps;
   a.eps24 = 24.0 * p.eps;
-  a.nu = p.nu;
   a.k3nu = (float)(3.0 * p.nu);
   a.k15nu = (float)(1.875 * p.nu);
   a.k075nu = (float)(0.75 * p.nu);
@@ -424,12 +599,20 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   a.ipart = (unsigned long long*)((double*)ctx->s.p[B_SRED] + 4 * (size_t)nb);
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_onesided, dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
+  if (wv)
+    hipLaunchKernelGGL((k_onesided<true, true>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
+  else if (wj)
+    hipLaunchKernelGGL((k_onesided<false, true>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL((k_onesided<false, false>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
   e = phase_end(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, ctx->stream, a.dpart, a.ipart, (int32_t)nb, p.nu, g.n[0],
                      g.n[1], g.n[2], res_dev);
-  return hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the candidates of the variant's cell sets, from the cell populations
+  // (B_SRED is free again once k_onesided_final has run)
+  return launch_variant_counts(ctx, g, p, res_dev, false);
 }
 
 }  // namespace atm3

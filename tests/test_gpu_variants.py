@@ -12,9 +12,9 @@ pytestmark = pytest.mark.gpu
 
 RC, NU = 2.5, 0.073
 
-# (truncation, variant, box side, molecules): boxes hold the cells each
-# combination needs (3 / 5 for 3c18 under the pairwise cutoff; 5 for the
-# product cutoff with 3c08, 7 with 3c18 and 3c01)
+# (truncation, variant, box side, molecules): at least 3 cells per dimension
+# (5 for 3c18); the product cases span the minimum-image regimes of the
+# one-sided kernel (both wraps, candidate-pair wrap only, none)
 CASES = [
     ("pair", "3c18", 13.0, 1000),
     ("pair", "3c01", 8.0, 330),
@@ -22,6 +22,11 @@ CASES = [
     ("product", "3c08", 13.0, 700),
     ("product", "3c18", 18.0, 900),
     ("product", "3c01", 18.0, 900),
+    ("product", "3c08", 8.0, 330),
+    ("product", "3c01", 8.0, 330),
+    ("product", "3c01", 10.5, 600),
+    ("product", "3c18", 13.0, 1000),
+    ("product", "3c08", 20.5, 1400),
 ]
 
 
@@ -78,4 +83,4 @@ def test_small_boxes_are_rejected(torch_cuda):
     with pytest.raises(ValueError, match="box too small"):
         atm3.compute_forces(p, box, variant="3c18")  # 4 cells < 5
     with pytest.raises(ValueError, match="box too small"):
-        atm3.compute_forces(p, box, truncation="product")  # 4 cells < 5
+        atm3.compute_forces(p, box, variant="3c18", truncation="product")
