@@ -42,7 +42,7 @@ extern "C" {
 #define ATM3_EDEVICE (-2)   /* HIP runtime error or bad device ordinal        */
 #define ATM3_ENOMEM (-3)    /* device allocation failed                       */
 #define ATM3_ERANGE (-4)    /* non-finite input, or a force beyond +-2^31     */
-#define ATM3_EOVERFLOW (-5) /* a 2x2x2 cell block holds more than 512 molecules */
+#define ATM3_EOVERFLOW (-5) /* too many molecules in a cell neighbourhood   */
 
 /* Truncation conditions of Sec. 2. */
 #define ATM3_TRUNC_PAIR 0    /* a triplet counts iff all three sides < rc        */
@@ -129,10 +129,11 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
  *   forces  device, n*3 FP32 output, input order, overwritten
  *   out     host result; the call blocks until the evaluation is done
  * Preconditions (ATM3_EINVAL otherwise): n >= 1; rc > 0; sigma > 0; every
- * n_d >= 3, and n_d >= 5 for the product rule with 3c08, n_d >= 7 for the
- * product rule with 3c18 or 3c01 (so cell shifts equal minimum images).
- * Returns ATM3_EOVERFLOW if some 2x2x2 block of cells holds more than 512
- * molecules, ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
+ * n_d >= 3 (the 27 neighbours of a cell are distinct), n_d >= 5 for 3c18.
+ * Every distance is the minimum image.  Returns ATM3_EOVERFLOW if some
+ * 2x2x2 block of cells holds more than 512 molecules (pair rule) or the
+ * cells within reach of one cell (1 cell, 2 for 3c18) hold more than 2048
+ * (product rule), ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
  * (forces are accumulated exactly in 64-bit fixed point with 2^-32
  * resolution); forces are undefined in both cases.  Results are
  * reproducible bit for bit between calls. */

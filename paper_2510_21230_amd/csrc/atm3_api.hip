@@ -132,7 +132,7 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
   if ((r = ensure(ctx, B_FPART, 8 * 24 * N))) return r;
   if ((r = ensure(ctx, B_BLKD, 8 * 3 * C))) return r;
   if ((r = ensure(ctx, B_BLKI, 4 * 2 * C))) return r;
-  if ((r = ensure(ctx, B_DEFER, 4 * (C + 2)))) return r;
+  if ((r = ensure(ctx, B_DEFER, 4 * (2 * C + 3)))) return r;
   if ((r = ensure(ctx, B_RED, reduce_scratch_bytes()))) return r;
   if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
   if (p->flags & ATM3_FLAG_CHECK_FINITE) {
@@ -295,7 +295,7 @@ int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const doubl
   if (out->status == ATM3_EOVERFLOW)
     return fail(ctx, out->status,
                 params->truncation == ATM3_TRUNC_PRODUCT
-                    ? "a molecule has more than 2048 candidate partners in its neighbour cells"
+                    ? "the cells within reach of a cell hold more than 2048 molecules"
                     : "a 2x2x2 block of cells holds more than 512 molecules");
   if (out->status == ATM3_ERANGE)
     return fail(ctx, out->status, "a force contribution or sum reached 2^31 (fixed-point accumulator range)");

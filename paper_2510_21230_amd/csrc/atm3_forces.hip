@@ -1013,7 +1013,8 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 }
 
 // Regular blocks; blocks with more than 128 molecules, more than PCAP upper
-// pairs or more than KCAP non-empty pairs are queued for k_block_big.
+// pairs, more than KCAP work items or a term beyond the rounding conversion
+// are queued (defer[2..]) for the wider tier k_block_wide.
 // Workgroup ids are spread over the 8 XCDs round-robin; consecutive ids on
 // one XCD map to consecutive base cells so neighbouring blocks share its L2.
 template <int PCAP, int KCAP>
@@ -1030,12 +1031,33 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
   }
 }
 
-template <int NW, int PCAP, int TCAP>
-__global__ __launch_bounds__(WG) void k_block_big(ForceArgs a) {
-  __shared__ LdsBig<NW, PCAP, TCAP> L;
+// The queued blocks again through the same path with room for the pair and
+// item counts of dense liquids (about 0.8 and above); what still does not
+// fit is queued (defer[ncells + 2..]) for k_block_big.
+template <int PCAP, int KCAP>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_block_wide(ForceArgs a) {
+  __shared__ LdsFast<PCAP, KCAP> L;
+  int32_t* q2 = a.defer + 2 + a.ncells;
   const int nq = a.defer[0];
   for (int q = blockIdx.x; q < nq; q += gridDim.x) {
     const int b = a.defer[2 + q];
+    if (!do_block_fast<PCAP, KCAP>(a, b, L)) {
+      if (threadIdx.x == 0) {
+        const int t = atomicAdd(&q2[0], 1);
+        q2[1 + t] = b;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NW, int PCAP, int TCAP>
+__global__ __launch_bounds__(WG) void k_block_big(ForceArgs a) {
+  __shared__ LdsBig<NW, PCAP, TCAP> L;
+  const int32_t* q2 = a.defer + 2 + a.ncells;
+  const int nq = q2[0];
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const int b = q2[1 + q];
     if (!do_block_big<NW, PCAP, TCAP>(a, b, L)) {
       if (threadIdx.x == 0) {
         atomicMin(&a.defer[1], ATM3_EOVERFLOW);
@@ -1048,10 +1070,11 @@ __global__ __launch_bounds__(WG) void k_block_big(ForceArgs a) {
   }
 }
 
-__global__ void k_reset(int32_t* defer) {
+__global__ void k_reset(int32_t* defer, int32_t ncells) {
   if (threadIdx.x == 0) {
     defer[0] = 0;
     defer[1] = ATM3_OK;
+    defer[2 + ncells] = 0;
   }
 }
 
@@ -1220,13 +1243,14 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   a.k15nu = (float)(1.875 * p.nu);
   a.k075nu = (float)(0.75 * p.nu);
 
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.defer);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.defer, a.ncells);
   const int per = (a.ncells + 7) / 8;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_block<1536, 768>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_block_wide<2560, 1016>), dim3(256), dim3(WG), 0, st, a);
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_REDUCE)) != hipSuccess) return e;

@@ -31,7 +31,7 @@ enum Buf {
   B_FPART,        // double[8][3][N] per-corner partial forces (sorted order)
   B_BLKD,         // double[C][3] per-block e_lj', w_lj', e_atm'
   B_BLKI,         // int32 [C][2] per-block pair and triplet counts
-  B_DEFER,        // int32 [C+2] [0] deferred count, [1] status, [2..] base cells
+  B_DEFER,        // int32 [2C+3] [0] count, [1] status, [2..C+2) queued base cells, [C+2] count, [C+3..) of the wide tier
   B_RED,          // first-stage reduction partials
   B_TILE,         // int32 per-tile sums of the cell-count scan
   // learned surrogate (atm3_surrogate.hip); slot = sorted molecule index

@@ -10,8 +10,8 @@
 // takes its own share, the triplet count becomes receiving incidences.
 //
 // Product cutoff: a triplet may have sides beyond rc, so there is no pair
-// filter.  k_onesided evaluates, one wave per molecule m, every pair (j, k)
-// of candidates from the cells around m (1 cell for 3c08 and 3c01, 2 for
+// filter.  k_onesided evaluates, for every molecule m, every pair (j, k) of
+// candidates from the cells around m (1 cell for 3c08 and 3c01, 2 for
 // 3c18): the visited-set test on the cell offsets, the truncation test on
 // the exact FP64 minimum-image squared sides (sorted, multiplied left to
 // right, strict), and the ATM force on m (FP32 per triplet, FP64 sums).

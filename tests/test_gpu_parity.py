@@ -284,6 +284,20 @@ def test_block_overflow_is_reported(torch_cuda):
     check_against(ref, f, r, terms=2)
 
 
+def test_dense_liquid_blocks_take_the_wide_tier(torch_cuda, orc):
+    """A dense disordered packing (rho 0.85, molecules 0.72 sigma apart at
+    least): many 2x2x2 blocks hold more than 1536 pairs within rc, more than
+    the regular blocks' lists take, and go through the wide tier."""
+    box = np.array([12.5, 12.5, 12.5])
+    pos, _ = workloads.rsa(1660, box, dmin=0.72, seed=workloads.SEED_BASE + 41)
+    _say(f"[dense liquid] n={len(pos)}")
+    ref = orc.brute(pos, box, rc=RC, nu=NU)
+    f, r = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU)
+    assert r["status"] == 0
+    check_against(ref, f, r)
+    assert r["n_candidates"] == ref.n_candidates
+
+
 @pytest.mark.parametrize("terms", [3, 1])
 def test_close_pair_takes_general_path(torch_cuda, orc, terms):
     """A pair at 0.5 sigma has an LJ force near 4e5, beyond the 2^18 range of
