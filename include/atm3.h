@@ -131,11 +131,13 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
  * Preconditions (ATM3_EINVAL otherwise): n >= 1; rc > 0; sigma > 0; every
  * n_d >= 3 (the 27 neighbours of a cell are distinct), n_d >= 5 for 3c18.
  * Every distance is the minimum image.  Returns ATM3_EOVERFLOW if some
- * 2x2x2 block of cells holds more than 512 molecules (pair rule) or the
- * cells within reach of one cell (1 cell, 2 for 3c18) hold more than 2048
- * (product rule), ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
- * (forces are accumulated exactly in 64-bit fixed point with 2^-32
- * resolution); forces are undefined in both cases.  Results are
+ * 2x2x2 block of cells holds more than 512 molecules (pair rule), or, under
+ * the product rule, the 27 cells around one cell hold more than 2048 or
+ * one 3c08 / 3c18 cell set more than 512.
+ * Returns ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
+ * (pair rule) or an ATM force term reaches 2^18 (product rule with 3c08 /
+ * 3c18).  Forces are accumulated exactly in 64-bit fixed point with 2^-32
+ * resolution and are undefined after either error.  Results are
  * reproducible bit for bit between calls. */
 int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                         const atm3_params* params, float* forces, atm3_result* out);

@@ -295,10 +295,13 @@ int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const doubl
   if (out->status == ATM3_EOVERFLOW)
     return fail(ctx, out->status,
                 params->truncation == ATM3_TRUNC_PRODUCT
-                    ? "the cells within reach of a cell hold more than 2048 molecules"
+                    ? "the cells within reach of a cell hold more than 2048 molecules, or a 3c08 / 3c18 cell set more than 512"
                     : "a 2x2x2 block of cells holds more than 512 molecules");
   if (out->status == ATM3_ERANGE)
-    return fail(ctx, out->status, "a force contribution or sum reached 2^31 (fixed-point accumulator range)");
+    return fail(ctx, out->status,
+                params->truncation == ATM3_TRUNC_PRODUCT
+                    ? "an ATM force term reached 2^18 (fixed-point accumulator range)"
+                    : "a force contribution or sum reached 2^31 (fixed-point accumulator range)");
   if (out->status != ATM3_OK) return fail(ctx, out->status, "evaluation failed");
   return ATM3_OK;
 }

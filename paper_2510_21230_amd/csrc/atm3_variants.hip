@@ -141,6 +141,7 @@ struct OneArgs {
   float rc2hi, lo6f, hi6f, small2;  // FP32 thresholds of the exact decisions
   float k3nu, k15nu, k075nu;
   float* forces;
+  double* fout;               // if set, FP64 forces go here instead of `forces`
   double* dpart;              // per block: e_lj, w_lj, e_atm, unused
   unsigned long long* ipart;  // per block: n_pairs, n_triplets, unused, overflow
 };
@@ -440,7 +441,10 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
           double s[3] = {0.0, 0.0, 0.0};
           for (int hh = 0; hh < OS_SPLIT; ++hh)
             for (int d = 0; d < 3; ++d) s[d] += L.facc[threadIdx.x * OS_SPLIT + hh][d];
-          for (int d = 0; d < 3; ++d) a.forces[3 * (int64_t)om + d] = (float)s[d];
+          for (int d = 0; d < 3; ++d) {
+            if (a.fout) a.fout[3 * (int64_t)om + d] = s[d];
+            else a.forces[3 * (int64_t)om + d] = (float)s[d];
+          }
         }
       }
       __syncthreads();
@@ -480,10 +484,282 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// product cutoff, 3c08 and 3c18: one block per base cell, each triplet once
+// ---------------------------------------------------------------------------
+// The cell set of base cell b is staged in LDS (3c08: the 2x2x2 block with b
+// as its minimum corner; 3c18: b and its 13 lexicographically greater
+// neighbours, b first).  A staged triplet i < j < k belongs to b iff its
+// corner codes AND to zero (3c08) or i lies in b (3c18; every other staged
+// cell is lexicographically greater than b).  Waves take the rows (i, j)
+// (j = wave mod 4), lanes the third molecules k > j; FP32 pre-test, queue and
+// exact decision as in the one-sided kernel; the ATM force on all three
+// molecules from the three minimum-image vectors (eq. forcepairs), rounded to
+// 2^-32 fixed point and summed with integer atomics (LDS per block, then
+// global per molecule), so the sums are exact and reproducible.
+constexpr int PB_CAP = 512;   // molecules of one cell set
+constexpr int PB_WAVES = 4;
+constexpr int PB_QCAP = 128;
+constexpr double FIX_SCALE = 4294967296.0;  // 2^32
+constexpr float PB_FIX_LIMIT = 262144.f;    // 2^18: a contribution beyond is reported
+
+struct ProdArgs {
+  const double4* sorted;
+  const int32_t* start;
+  const double* pos;
+  int32_t nx, ny, nz, splits;  // `splits` blocks share a base cell's rows
+  double side[3], box[3];
+  double rc6;
+  float boxf[3], invf[3];
+  float lo6f, hi6f, small2;
+  float k3nu, k15nu, k075nu;
+  unsigned long long* acc;    // [3 n] fixed-point ATM forces, input order
+  double* dpart;              // per block: 0, 0, 3 sum u, 0
+  unsigned long long* ipart;  // per block: 0, n_triplets, range flag, overflow
+};
+
+struct ProdLds {
+  float4 p[PB_CAP];  // position relative to the base cell's centre; .w = input index
+  uint8_t code[PB_CAP];
+  unsigned long long f[3][PB_CAP];
+  uint32_t q[PB_WAVES][PB_QCAP];  // queued triplets i | j << 9 | k << 18
+  int32_t cnt[16], base[16], cell[16];
+  double red[PB_WAVES];
+  unsigned long long redi[PB_WAVES][2];
+};
+
+// eq. (atm) and eq. (forcepairs) from the three pair vectors r_ij = r_i - r_j,
+// r_ik, r_jk and their squared lengths x, y, z: F_i = c_x r_ij + c_y r_ik,
+// F_j = -c_x r_ij + c_z r_jk (F_k = -F_i - F_j); returns u / nu.
+__device__ __forceinline__ float atm_vec(float3 ij, float3 ik, float3 jk, float x, float y, float z, float k3nu,
+                                         float k15nu, float k075nu, float3* fi, float3* fj) {
+  const float s = x + y + z;
+  const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
+  const float AB = A * B, AC = A * C, BC = B * C;
+  const float P = AB * C;
+  const float S = AB + AC + BC;
+  const float xy = x * y, yz = y * z, xz = x * z;
+  const float Q = xy * z;
+  const float t1 = __builtin_amdgcn_rsqf(Q);
+  const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
+  const float G = fmaf(k15nu * P, t5, k3nu * t3);
+  const float H = k075nu * t5;
+  const float cx = fmaf(G, yz * t2, -H * fmaf(-2.f, BC, S));
+  const float cy = fmaf(G, xz * t2, -H * fmaf(-2.f, AC, S));
+  const float cz = fmaf(G, xy * t2, -H * fmaf(-2.f, AB, S));
+  fi->x = fmaf(cx, ij.x, cy * ik.x);
+  fi->y = fmaf(cx, ij.y, cy * ik.y);
+  fi->z = fmaf(cx, ij.z, cy * ik.z);
+  fj->x = fmaf(cz, jk.x, -cx * ij.x);
+  fj->y = fmaf(cz, jk.y, -cx * ij.y);
+  fj->z = fmaf(cz, jk.z, -cx * ij.z);
+  return fmaf(0.375f * P, t5, t3);
+}
+
+__device__ __forceinline__ unsigned long long fix32(float v) {
+  return (unsigned long long)(long long)rint((double)v * FIX_SCALE);
+}
+
+template <int VAR, bool WR>
+__global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
+  __shared__ ProdLds L;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t b = blockIdx.x / a.splits;
+  const int split = blockIdx.x % a.splits;
+  const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((int64_t)a.nx * a.ny));
+  constexpr int NCS = (VAR == ATM3_VARIANT_3C08) ? 8 : 14;
+  // offsets of the cell set; 3c18: base, then the forward half in z-major order
+  auto offs = [](int q, int& dx, int& dy, int& dz) {
+    if (VAR == ATM3_VARIANT_3C08) {
+      dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+    } else {
+      const int t = q == 0 ? 13 : 13 + q;  // index in the 27-cube, z-major
+      dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    }
+  };
+  if (threadIdx.x < NCS) {
+    int dx, dy, dz;
+    offs(threadIdx.x, dx, dy, dz);
+    const int ux = wrapc(bx + dx, a.nx), uy = wrapc(by + dy, a.ny), uz = wrapc(bz + dz, a.nz);
+    const int cc = (uz * a.ny + uy) * a.nx + ux;
+    L.cell[threadIdx.x] = cc;
+    L.cnt[threadIdx.x] = a.start[cc + 1] - a.start[cc];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int q = 0; q < NCS; ++q) {
+      L.base[q] = s;
+      s += L.cnt[q];
+    }
+    L.base[NCS] = s;
+  }
+  __syncthreads();
+  const int n = L.base[NCS];
+  double e3 = 0.0;
+  unsigned long long ntrip = 0, rng = 0;
+  const unsigned long long over = n > PB_CAP ? 1 : 0;
+  if (!over) {
+    for (int q = w; q < NCS; q += PB_WAVES) {
+      int dx, dy, dz;
+      offs(q, dx, dy, dz);
+      const int t0 = a.start[L.cell[q]], m = L.cnt[q], bb = L.base[q];
+      const uint8_t code = (VAR == ATM3_VARIANT_3C08) ? (uint8_t)q : (uint8_t)(q == 0 ? 0 : 1);
+      for (int t = lane; t < m; t += 64) {
+        const double4 o = a.sorted[t0 + t];
+        L.p[bb + t] = make_float4((float)(o.x + dx * a.side[0]), (float)(o.y + dy * a.side[1]),
+                                  (float)(o.z + dz * a.side[2]), __int_as_float((int)o.w));
+        L.code[bb + t] = code;
+      }
+    }
+    for (int t = threadIdx.x; t < n; t += 64 * PB_WAVES) L.f[0][t] = L.f[1][t] = L.f[2][t] = 0ull;
+  }
+  __syncthreads();
+  if (!over) {
+    auto dvec = [&](const float4 u, const float4 v) {  // minimum image of u - v
+      float3 d = make_float3(u.x - v.x, u.y - v.y, u.z - v.z);
+      if (WR) d = wrapf(d, a.boxf, a.invf);
+      return d;
+    };
+    uint32_t* qb = L.q[w];
+    int qn = 0;
+    auto drain = [&](int cnt) {
+      if (lane < cnt) {
+        const uint32_t e = qb[qn - cnt + lane];
+        const int i = (int)(e & 511u), j = (int)((e >> 9) & 511u), k = (int)(e >> 18);
+        const float4 pi = L.p[i], pj = L.p[j], pk = L.p[k];
+        const float3 ij = dvec(pi, pj), ik = dvec(pi, pk), jk = dvec(pj, pk);
+        const float x = sq3(ij), y = sq3(ik), z = sq3(jk);
+        bool in = true;
+        if (!((x * y) * z < a.lo6f) || fminf(x, fminf(y, z)) < a.small2) {
+          const int oi = __float_as_int(pi.w), oj = __float_as_int(pj.w), ok = __float_as_int(pk.w);
+          in = product_ok(exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]),
+                          exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]),
+                          exact_r2(a.pos, oj, ok, a.box[0], a.box[1], a.box[2]), a.rc6);
+        }
+        if (in) {
+          float3 fi, fj;
+          const float u = atm_vec(ij, ik, jk, x, y, z, a.k3nu, a.k15nu, a.k075nu, &fi, &fj);
+          const float3 fk = make_float3(-(fi.x + fj.x), -(fi.y + fj.y), -(fi.z + fj.z));
+          const float mx = fmaxf(fmaxf(fmaxf(fabsf(fi.x), fabsf(fi.y)), fmaxf(fabsf(fi.z), fabsf(fj.x))),
+                                 fmaxf(fmaxf(fabsf(fj.y), fabsf(fj.z)),
+                                       fmaxf(fabsf(fk.x), fmaxf(fabsf(fk.y), fabsf(fk.z)))));
+          if (!(mx < PB_FIX_LIMIT)) {
+            rng = 1;
+          } else {
+            atomicAdd(&L.f[0][i], fix32(fi.x));
+            atomicAdd(&L.f[1][i], fix32(fi.y));
+            atomicAdd(&L.f[2][i], fix32(fi.z));
+            atomicAdd(&L.f[0][j], fix32(fj.x));
+            atomicAdd(&L.f[1][j], fix32(fj.y));
+            atomicAdd(&L.f[2][j], fix32(fj.z));
+            atomicAdd(&L.f[0][k], fix32(fk.x));
+            atomicAdd(&L.f[1][k], fix32(fk.y));
+            atomicAdd(&L.f[2][k], fix32(fk.z));
+          }
+          e3 += 3.0 * (double)u;
+          ++ntrip;
+        }
+      }
+      qn -= cnt;
+    };
+    const int imax = (VAR == ATM3_VARIANT_3C08) ? n : min(n, L.cnt[0]);
+    // rows (i, j) with j = split * PB_WAVES + wave modulo splits * PB_WAVES
+    const int stride = a.splits * PB_WAVES, mine = split * PB_WAVES + w;
+    for (int i = 0; i < imax; ++i) {
+      const float4 pi = L.p[i];
+      const int ci = L.code[i];
+      int j = i + 1 + (((mine - (i + 1)) % stride) + stride) % stride;
+      for (; j + 1 < n; j += stride) {
+        const float4 pj = L.p[j];
+        const int cij = ci & L.code[j];
+        const float3 ij = dvec(pi, pj);
+        const float x = sq3(ij);
+        for (int k0 = j + 1; k0 < n; k0 += 64) {
+          const int k = k0 + lane;
+          bool acc = false;
+          if (k < n && (VAR != ATM3_VARIANT_3C08 || (L.code[k] & cij) == 0)) {
+            const float4 pk = L.p[k];
+            const float y = sq3(dvec(pi, pk)), z = sq3(dvec(pj, pk));
+            acc = (x * y) * z < a.hi6f || fminf(x, fminf(y, z)) < a.small2;
+          }
+          const unsigned long long bits = __ballot(acc);
+          if (acc)
+            qb[qn + __popcll(bits & ((1ull << lane) - 1ull))] =
+                (uint32_t)i | ((uint32_t)j << 9) | ((uint32_t)k << 18);
+          qn += __popcll(bits);
+          __builtin_amdgcn_wave_barrier();
+          if (qn >= 64) {
+            drain(64);
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+      }
+    }
+    if (qn > 0) drain(qn);
+  }
+  __syncthreads();
+  if (!over) {
+    for (int t = threadIdx.x; t < n; t += 64 * PB_WAVES) {
+      const int o = __float_as_int(L.p[t].w);
+      for (int d = 0; d < 3; ++d) {
+        const unsigned long long v = L.f[d][t];
+        if (v) atomicAdd(&a.acc[3 * (int64_t)o + d], v);
+      }
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    e3 += __shfl_xor(e3, o);
+    ntrip += __shfl_xor(ntrip, o);
+    rng |= __shfl_xor(rng, o);
+  }
+  if (lane == 0) {
+    L.red[w] = e3;
+    L.redi[w][0] = ntrip;
+    L.redi[w][1] = rng;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    unsigned long long t = 0, r = 0;
+    for (int q = 0; q < PB_WAVES; ++q) {
+      s += L.red[q];
+      t += L.redi[q][0];
+      r |= L.redi[q][1];
+    }
+    const int64_t blk = blockIdx.x;
+    a.dpart[4 * blk + 0] = 0.0;
+    a.dpart[4 * blk + 1] = 0.0;
+    a.dpart[4 * blk + 2] = s;
+    a.dpart[4 * blk + 3] = 0.0;
+    a.ipart[4 * blk + 0] = 0;
+    a.ipart[4 * blk + 1] = t;
+    a.ipart[4 * blk + 2] = r;
+    a.ipart[4 * blk + 3] = over;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, int64_t m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) p[i] = 0ull;
+}
+
+// forces = FP64 LJ force (when computed) + fixed-point ATM force, rounded once.
+__global__ __launch_bounds__(256) void k_prod_forces(const double* __restrict__ lj,
+                                                     const unsigned long long* __restrict__ acc, int64_t m,
+                                                     float* __restrict__ forces) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double f3 = (double)(long long)acc[i] * (1.0 / FIX_SCALE);
+  forces[i] = (float)(lj ? lj[i] + f3 : f3);
+}
+
 // Fixed-order sums of the per-block partials into the result.  The ATM
-// energy collected per molecule is the sum over triplets of u / nu counted
-// once per receiving molecule, so E3 = nu * sum / 3; W3 = 9 E3 (the ATM
-// potential is homogeneous of degree -9 in the positions).
+// energy partials hold 3 u / nu per triplet (once per receiving molecule in
+// the one-sided kernel, three times u once per triplet in the block kernel),
+// so E3 = nu * sum / 3; W3 = 9 E3 (the ATM potential is homogeneous of
+// degree -9 in the positions).  Integer slot 2 flags a force contribution
+// beyond the fixed-point range.
 __global__ __launch_bounds__(256) void k_onesided_final(const double* __restrict__ dpart,
                                                         const unsigned long long* __restrict__ ipart, int32_t nb,
                                                         double nu, int32_t nx, int32_t ny, int32_t nz,
@@ -516,11 +792,11 @@ __global__ __launch_bounds__(256) void k_onesided_final(const double* __restrict
   r.w_atm = 9.0 * r.e_atm;
   r.n_pairs = (int64_t)si[0][0];
   r.n_triplets = (int64_t)si[1][0];
-  r.n_candidates = (int64_t)si[2][0];
+  r.n_candidates = 0;  // from the cell populations afterwards
   r.ncell[0] = nx;
   r.ncell[1] = ny;
   r.ncell[2] = nz;
-  r.status = si[3][0] ? ATM3_EOVERFLOW : ATM3_OK;
+  r.status = si[3][0] ? ATM3_EOVERFLOW : (si[2][0] ? ATM3_ERANGE : ATM3_OK);
   *res = r;
 }
 
@@ -544,20 +820,14 @@ hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params
   return hipGetLastError();
 }
 
-hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
-                           float* forces, atm3_result* res_dev) {
-  const int reach = (p.variant == ATM3_VARIANT_3C18) ? 2 : 1;
-  // group slices per cell: about one group of OS_MOLS molecules per block
+namespace {
+
+// One-sided kernel arguments for `terms`, reach 1 (LJ only) or the variant's.
+OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p, int terms,
+                 int reach, float* forces, int* groups_out, bool* wv, bool* wj) {
+  OneArgs a;
   const int64_t per_cell = (n + g.ncells - 1) / g.ncells;
   const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
-  const int64_t nb64 = g.ncells * groups;
-  if (nb64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-  const unsigned nb = (unsigned)nb64;
-  // room for the per-block partials and, afterwards, the candidate partials
-  // of launch_variant_counts (so that its ensure does not reallocate)
-  const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
-  if (ensure(ctx, B_SRED, need > need_c ? need : need_c)) return hipErrorOutOfMemory;
-  OneArgs a;
   a.sorted = (const double4*)ctx->s.p[B_SORTED];
   a.start = (const int32_t*)ctx->s.p[B_START];
   a.pos = pos;
@@ -566,18 +836,18 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   a.nz = g.n[2];
   a.reach = reach;
   a.variant = p.variant;
-  a.terms = p.terms;
+  a.terms = terms;
   a.groups = groups;
   double smin = g.side[0];
-  bool wv = false, wj = false;
+  *wv = *wj = false;
   for (int d = 0; d < 3; ++d) {
     a.side[d] = g.side[d];
     a.box[d] = g.box[d];
     a.boxf[d] = (float)g.box[d];
     a.invf[d] = (float)(1.0 / g.box[d]);
     smin = std::min(smin, g.side[d]);
-    wv = wv || g.n[d] < 2 * (reach + 1);
-    wj = wj || g.n[d] < 4 * (reach + 1);
+    *wv = *wv || g.n[d] < 2 * (reach + 1);
+    *wj = *wj || g.n[d] < 4 * (reach + 1);
   }
   a.rc2 = p.rc * p.rc;
   a.rc6 = (a.rc2 * a.rc2) * a.rc2;
@@ -595,20 +865,104 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   a.k15nu = (float)(1.875 * p.nu);
   a.k075nu = (float)(0.75 * p.nu);
   a.forces = forces;
-  a.dpart = (double*)ctx->s.p[B_SRED];
-  a.ipart = (unsigned long long*)((double*)ctx->s.p[B_SRED] + 4 * (size_t)nb);
+  a.fout = nullptr;
+  *groups_out = groups;
+  return a;
+}
+
+void launch_one(const OneArgs& a, unsigned nb, bool wv, bool wj, hipStream_t st) {
+  if (wv)
+    hipLaunchKernelGGL((k_onesided<true, true>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+  else if (wj)
+    hipLaunchKernelGGL((k_onesided<false, true>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_onesided<false, false>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+}
+
+}  // namespace
+
+hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
+                           float* forces, atm3_result* res_dev) {
+  const bool lj = (p.terms & ATM3_TERM_LJ) != 0, atm = (p.terms & ATM3_TERM_ATM) != 0;
+  // 3c01 (every molecule takes its own share) runs the one-sided kernel for
+  // both terms; 3c08 and 3c18 run it for LJ only (reach 1) and the block
+  // kernel for ATM
+  const bool blockwise = p.variant != ATM3_VARIANT_3C01;
+  const int reach = (!blockwise && p.variant == ATM3_VARIANT_3C18) ? 2 : 1;
+  const int one_terms = blockwise ? (p.terms & ATM3_TERM_LJ) : p.terms;
+  int groups = 1;
+  bool wv = false, wj = false;
+  OneArgs a = one_args(ctx, pos, n, g, p, one_terms, reach, forces, &groups, &wv, &wj);
+  const int64_t nb1_64 = one_terms ? g.ncells * groups : 0;
+  // small grids: several blocks per base cell so that about 2048 run
+  const int splits = (int)std::min<int64_t>(8, std::max<int64_t>(1, (2048 + g.ncells - 1) / g.ncells));
+  const int64_t nb2_64 = (blockwise && atm) ? g.ncells * splits : 0;
+  if (nb1_64 + nb2_64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  const unsigned nb1 = (unsigned)nb1_64, nb2 = (unsigned)nb2_64, nb = nb1 + nb2;
+  // room for the per-block partials and, afterwards, the candidate partials
+  // of launch_variant_counts (so that its ensure does not reallocate)
+  const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
+  if (ensure(ctx, B_SRED, need > need_c ? need : need_c)) return hipErrorOutOfMemory;
+  double* dpart = (double*)ctx->s.p[B_SRED];
+  unsigned long long* ipart = (unsigned long long*)(dpart + 4 * (size_t)nb);
+  // B_FPART (24 doubles per molecule) holds the fixed-point ATM forces and
+  // the FP64 LJ forces of the block path
+  unsigned long long* acc = (unsigned long long*)ctx->s.p[B_FPART];
+  double* ljf = (double*)(acc + 3 * n);
+  hipStream_t st = ctx->stream;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  if (wv)
-    hipLaunchKernelGGL((k_onesided<true, true>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
-  else if (wj)
-    hipLaunchKernelGGL((k_onesided<false, true>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
-  else
-    hipLaunchKernelGGL((k_onesided<false, false>), dim3(nb), dim3(64 * OS_WAVES), 0, ctx->stream, a);
+  if (blockwise)
+    hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st, acc, 3 * n);
+  if (nb1) {
+    a.dpart = dpart;
+    a.ipart = ipart;
+    if (blockwise) a.fout = ljf;
+    launch_one(a, nb1, wv, wj, st);
+  }
+  if (nb2) {
+    ProdArgs b;
+    b.sorted = a.sorted;
+    b.start = a.start;
+    b.pos = pos;
+    b.nx = g.n[0];
+    b.ny = g.n[1];
+    b.nz = g.n[2];
+    b.splits = splits;
+    bool wr = false;
+    for (int d = 0; d < 3; ++d) {
+      b.side[d] = a.side[d];
+      b.box[d] = a.box[d];
+      b.boxf[d] = a.boxf[d];
+      b.invf[d] = a.invf[d];
+      // vectors inside a cell set span under 2 (3c08) or 3 (3c18) cells
+      wr = wr || g.n[d] < (p.variant == ATM3_VARIANT_3C08 ? 4 : 6);
+    }
+    b.rc6 = a.rc6;
+    b.lo6f = a.lo6f;
+    b.hi6f = a.hi6f;
+    b.small2 = a.small2;
+    b.k3nu = a.k3nu;
+    b.k15nu = a.k15nu;
+    b.k075nu = a.k075nu;
+    b.acc = acc;
+    b.dpart = dpart + 4 * (size_t)nb1;
+    b.ipart = ipart + 4 * (size_t)nb1;
+    if (p.variant == ATM3_VARIANT_3C08) {
+      if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, true>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
+      else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, false>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
+    } else {
+      if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, true>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
+      else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, false>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
+    }
+  }
+  if (blockwise)
+    hipLaunchKernelGGL(k_prod_forces, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st, lj ? (const double*)ljf : nullptr,
+                       (const unsigned long long*)acc, 3 * n, forces);
   e = phase_end(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, ctx->stream, a.dpart, a.ipart, (int32_t)nb, p.nu, g.n[0],
-                     g.n[1], g.n[2], res_dev);
+  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, st, dpart, ipart, (int32_t)nb, p.nu, g.n[0], g.n[1],
+                     g.n[2], res_dev);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // the candidates of the variant's cell sets, from the cell populations
   // (B_SRED is free again once k_onesided_final has run)
