@@ -10,13 +10,17 @@
 // takes its own share, the triplet count becomes receiving incidences.
 //
 // Product cutoff: a triplet may have sides beyond rc, so there is no pair
-// filter.  k_onesided evaluates, for every molecule m, every pair (j, k) of
-// candidates from the cells around m (1 cell for 3c08 and 3c01, 2 for
-// 3c18): the visited-set test on the cell offsets, the truncation test on
-// the exact FP64 minimum-image squared sides (sorted, multiplied left to
-// right, strict), and the ATM force on m (FP32 per triplet, FP64 sums).
-// Energies and virials are credited a third per receiving molecule; counts
-// once per triplet (3c01: once per receiving molecule).
+// filter.  For 3c08 and 3c18, k_prod_block stages each base cell's cell set
+// and evaluates each of its triplets once (forces on all three, exact fixed
+// point).  For 3c01, where each molecule takes its own share, k_onesided
+// evaluates for every molecule m every pair (j, k) of candidates from the
+// 27 cells around m: the visited-set test on the cell offsets, the
+// truncation test on the exact FP64 minimum-image squared sides (sorted,
+// multiplied left to right, strict), and the ATM force on m (FP32 per
+// triplet, FP64 sums); it also gives the LJ forces of the other two.
+// Energies and virials are credited once per triplet (a third per receiving
+// molecule for 3c01); counts once per triplet (3c01: once per receiving
+// molecule).
 #include <math.h>
 
 #include <algorithm>
@@ -128,13 +132,13 @@ constexpr int OS_WAVES = 8;     // waves per block
 constexpr int OS_SPLIT = 2;     // waves per molecule (rows xa split by parity)
 constexpr int OS_MOLS = OS_WAVES / OS_SPLIT;  // molecules per group
 constexpr int OS_QCAP = 128;    // per-wave queue of pairs that passed the FP32 test
-constexpr int OS_MAXNB = 125;   // neighbour cells (reach 2)
+constexpr int OS_NB = 27;       // neighbour cells, the cell included
 
 struct OneArgs {
   const double4* sorted;
   const int32_t* start;
   const double* pos;
-  int32_t nx, ny, nz, reach, variant, terms, groups;
+  int32_t nx, ny, nz, variant, terms, groups;
   double side[3], box[3];
   double rc2, rc6, sig2, eps4, eps24;
   float boxf[3], invf[3];
@@ -248,8 +252,8 @@ struct OneLds {
   float4 p[CAND_CAP];         // candidate position relative to the centre cell's centre; .w = input index
   uint32_t off[CAND_CAP];     // packed cell offset (dx+8) | (dy+8) << 8 | (dz+8) << 16
   uint32_t q[OS_WAVES][OS_QCAP];  // queued pairs xa | xb << 16
-  int32_t cnt[OS_MAXNB + 3], base[OS_MAXNB + 3];
-  int32_t cell[OS_MAXNB + 3];
+  int32_t cnt[OS_NB + 1], base[OS_NB + 1];
+  int32_t cell[OS_NB + 1];
   double facc[OS_WAVES][3];
   double red[OS_WAVES][3];
   unsigned long long redi[OS_WAVES][2];
@@ -262,9 +266,8 @@ struct OneLds {
 // parity), each lane taking the partners xb > xa of row xa.  Pairs that pass
 // the FP32 product test with a relative guard band are queued and evaluated
 // 64 at a time; pairs inside the band take the oracle's FP64 decision.  WV:
-// molecule-candidate vectors need a minimum-image wrap (fewer than
-// 2 (reach + 1) cells per dimension); WJ: candidate-candidate vectors do
-// (fewer than 4 (reach + 1)).
+// molecule-candidate vectors need a minimum-image wrap (fewer than 4 cells
+// per dimension); WJ: candidate-candidate vectors do (fewer than 8).
 template <bool WV, bool WJ>
 __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   __shared__ OneLds L;
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   const int64_t c = blockIdx.x / a.groups;
   const int g = blockIdx.x % a.groups;
   const int cx = (int)(c % a.nx), cy = (int)((c / a.nx) % a.ny), cz = (int)(c / ((int64_t)a.nx * a.ny));
-  const int R = a.reach, span = 2 * R + 1, nnb = span * span * span, q0 = (nnb - 1) / 2;
+  constexpr int R = 1, span = 3, nnb = OS_NB, q0 = 13;
   double e_lj = 0.0, w_lj = 0.0, e3 = 0.0;
   unsigned long long npair = 0, ntrip = 0, over = 0;
   // neighbour cells (dx fastest) and their populations
@@ -822,9 +825,9 @@ hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params
 
 namespace {
 
-// One-sided kernel arguments for `terms`, reach 1 (LJ only) or the variant's.
+// One-sided kernel arguments for `terms`.
 OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p, int terms,
-                 int reach, float* forces, int* groups_out, bool* wv, bool* wj) {
+                 float* forces, int* groups_out, bool* wv, bool* wj) {
   OneArgs a;
   const int64_t per_cell = (n + g.ncells - 1) / g.ncells;
   const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
@@ -834,7 +837,6 @@ OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, con
   a.nx = g.n[0];
   a.ny = g.n[1];
   a.nz = g.n[2];
-  a.reach = reach;
   a.variant = p.variant;
   a.terms = terms;
   a.groups = groups;
@@ -846,8 +848,9 @@ OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, con
     a.boxf[d] = (float)g.box[d];
     a.invf[d] = (float)(1.0 / g.box[d]);
     smin = std::min(smin, g.side[d]);
-    *wv = *wv || g.n[d] < 2 * (reach + 1);
-    *wj = *wj || g.n[d] < 4 * (reach + 1);
+    // molecule-partner vectors span under 2 cells, partner-partner under 4
+    *wv = *wv || g.n[d] < 4;
+    *wj = *wj || g.n[d] < 8;
   }
   a.rc2 = p.rc * p.rc;
   a.rc6 = (a.rc2 * a.rc2) * a.rc2;
@@ -885,14 +888,13 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
                            float* forces, atm3_result* res_dev) {
   const bool lj = (p.terms & ATM3_TERM_LJ) != 0, atm = (p.terms & ATM3_TERM_ATM) != 0;
   // 3c01 (every molecule takes its own share) runs the one-sided kernel for
-  // both terms; 3c08 and 3c18 run it for LJ only (reach 1) and the block
+  // both terms; 3c08 and 3c18 run it for LJ only and the block
   // kernel for ATM
   const bool blockwise = p.variant != ATM3_VARIANT_3C01;
-  const int reach = (!blockwise && p.variant == ATM3_VARIANT_3C18) ? 2 : 1;
   const int one_terms = blockwise ? (p.terms & ATM3_TERM_LJ) : p.terms;
   int groups = 1;
   bool wv = false, wj = false;
-  OneArgs a = one_args(ctx, pos, n, g, p, one_terms, reach, forces, &groups, &wv, &wj);
+  OneArgs a = one_args(ctx, pos, n, g, p, one_terms, forces, &groups, &wv, &wj);
   const int64_t nb1_64 = one_terms ? g.ncells * groups : 0;
   // small grids: several blocks per base cell so that about 2048 run
   const int splits = (int)std::min<int64_t>(8, std::max<int64_t>(1, (2048 + g.ncells - 1) / g.ncells));

@@ -11,10 +11,12 @@ LJ tail corrections for energy and pressure (g(r) = 1 beyond rc); no tail
 correction for ATM.  P = 2 KE/(3V) + (W_LJ + W_ATM)/(3V) + P_tail.
 
 The run is deterministic (bit-reproducible forces), so the tolerances only
-have to cover the sampling error of a 25,000-step average (block standard
-errors of this run: about 0.001 in E/N and 0.004 in P) and the different
-thermostat: E/N within 0.01 and P within 0.03 of the printed values, and the
-three-body shifts (nu = 0.072 minus nu = 0) within 5 %.  With the pair rule
+have to cover the sampling error of a 25,000-step average and the different
+thermostat.  Block standard errors are about 0.001 in E/N and 0.004 in P,
+but two runs of one protocol whose forces differ only in summation order
+(a kernel change) differ by up to 0.003 in E/N and 0.008 in P.  Hence: E/N
+within 0.01 and P within 0.03 of the printed values; the three-body shift
+(nu = 0.072 minus nu = 0) of E/N within 5 %, that of P within 0.02.  With the pair rule
 all traversals include the same triplets (the printed traversal rows differ
 only by sampling), so the 3c08 row is the comparison.  The product rule is
 run from the same nu = 0 state with each of the three cell sets and compared
@@ -82,4 +84,4 @@ def test_single_phase_table(state):
         assert abs(e3 - ref3["E_per_N"]) < 0.01 and abs(p3 - ref3["P"]) < 0.03
         de, dp = e3 - e0, p3 - p0
         rde, rdp = ref3["E_per_N"] - ref0["E_per_N"], ref3["P"] - ref0["P"]
-        assert abs(de - rde) < 0.05 * abs(rde) and abs(dp - rdp) < 0.05 * abs(rdp), (de, rde, dp, rdp)
+        assert abs(de - rde) < 0.05 * abs(rde) and abs(dp - rdp) < 0.02, (de, rde, dp, rdp)
