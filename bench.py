@@ -148,6 +148,47 @@ def surrogate_leg(pos, box, f_exact, params, args):
     return out
 
 
+def rc_study(args):
+    """Cost against the cutoff (the paper's motivation for a surrogate: the
+    exact triplet work grows as rc^6, the surrogate's pair work as rc^3).
+    For each rc: one evaluation of exact LJ+ATM under the pair rule and under
+    the product rule (3c08 sets), and of LJ plus the learned three-body
+    surrogate (untrained weights, no exact fallback: its cost does not depend
+    on the weights), on the same system.  Prints one JSON line per (rc, path)
+    with the mean time of `--steps` evaluations after `--warmup`."""
+    import torch
+
+    import paper_2510_21230_amd as atm3
+    from paper_2510_21230_amd import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pos_np, box = workloads.make(args.workload)
+    pos = torch.from_numpy(pos_np).to(dev)
+    n = len(pos_np)
+    ctx = atm3.context(0)
+    mlp = atm3.Mlp(seed=1, device=0)
+    forces = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    for rc in [float(x) for x in args.study_rc.split(",")]:
+        runs = [("exact pair rule", lambda: ctx.compute_forces(pos, box, forces, rc=rc, nu=0.073)),
+                ("exact product rule 3c08", lambda: ctx.compute_forces(pos, box, forces, rc=rc, nu=0.073,
+                                                                     truncation="product")),
+                ("LJ + surrogate", lambda: mlp.forces(pos, box, rc=rc, nu=0.073, forces=forces))]
+        for name, fn in runs:
+            for _ in range(args.warmup):
+                out = fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                out = fn()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.steps
+            r = out[1]
+            print(json.dumps({"study": "cost against rc", "workload": args.workload, "n": n, "rc": rc,
+                              "path": name, "ms_per_evaluation": ms, "molecule_updates_per_s": n / ms * 1e3,
+                              "n_pairs": r["n_pairs"], "n_triplets": r["n_triplets"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,7 +202,12 @@ def main():
     ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--study-rc", default="",
+                    help="comma-separated cutoffs: print the cost-against-rc study instead of the benchmark line")
     args = ap.parse_args()
+    if args.study_rc:
+        rc_study(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
