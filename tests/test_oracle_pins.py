@@ -412,3 +412,56 @@ def test_binning_edge_cases(orc):
     # L / rc just above an integer
     n = orc.grid(np.array([10.000001, 12.5, 7.4999]), RC)
     assert list(n) == [4, 5, 2]
+
+
+# --------------------------------------------------------------------------
+# planar long-range correction of the LJ force (slab runs, Sec. 5.2)
+# --------------------------------------------------------------------------
+def _sheet_force_by_quadrature(xi, areal, rc, eps=1.0, sigma=1.0):
+    """The definition integrated numerically: every molecule of a uniform
+    sheet farther than rc pulls with the LJ pair force f(r) along the
+    separation; only the z-components survive the lateral integral."""
+    from scipy.integrate import quad
+
+    def f(r):  # LJ pair force magnitude, positive when repulsive
+        return 24.0 * eps * (2.0 * sigma ** 12 / r ** 13 - sigma ** 6 / r ** 7)
+
+    s0 = np.sqrt(max(0.0, rc * rc - xi * xi))
+    val, _ = quad(lambda s: f(np.hypot(s, xi)) * xi / np.hypot(s, xi) * 2.0 * np.pi * s, s0, np.inf,
+                  epsabs=1e-14, epsrel=1e-12, limit=400)
+    return areal * val
+
+
+@pytest.mark.parametrize("xi", [0.3, 1.7, -2.2, 2.5, 2.9, -4.1, 7.0])
+def test_sheet_force_matches_quadrature(xi):
+    from oracle import slab
+    got = float(slab.sheet_force(xi, 0.37, 2.5))
+    ref = _sheet_force_by_quadrature(xi, 0.37, 2.5)
+    assert got == pytest.approx(ref, rel=1e-9, abs=1e-13)
+
+
+def test_lrc_vanishes_for_uniform_density_and_flips_under_mirror():
+    from oracle import slab
+    box = np.array([6.0, 5.0, 30.0])
+    nb = 61
+    # one molecule at the centre of every bin: uniform profile, the force on
+    # each (at a bin centre) cancels pairwise (an odd bin count leaves no bin
+    # at exactly half the box, whose minimum image is a tie)
+    z = (np.arange(nb) + 0.5) * box[2] / nb
+    pos = np.stack([np.full(nb, 1.0), np.full(nb, 2.0), z], axis=1)
+    fz, hist = slab.lrc_forces(pos, box, nb, 2.5)
+    assert (hist == 1).all()
+    assert np.abs(fz).max() < 1e-12
+    # a slab: mirroring z -> L_z - z mirrors the profile and flips the force
+    rng = np.random.default_rng(5)
+    p = np.concatenate([rng.uniform([0, 0, 10], [6, 5, 20], (300, 3)), rng.uniform([0, 0, 0], [6, 5, 30], (20, 3))])
+    fz1, _ = slab.lrc_forces(p, box, 600, 2.5)
+    q = p.copy()
+    q[:, 2] = box[2] - p[:, 2]
+    fz2, _ = slab.lrc_forces(q, box, 600, 2.5)
+    # bins mirror exactly only when no molecule sits on a bin edge; compare
+    # with the tolerance of one bin width of displacement
+    assert np.allclose(fz2, -fz1, atol=5e-3 * np.abs(fz1).max())
+    # molecules inside the slab near its lower face are pulled up (+z)
+    near = (p[:, 2] > 10.5) & (p[:, 2] < 12.0)
+    assert (fz1[near] > 0).mean() > 0.9
