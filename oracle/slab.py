@@ -16,6 +16,9 @@ with phi(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6] and f = -phi' (the lateral
 integral of f xi / r over r from R to infinity is xi (phi(R) - 0)).  The
 density profile is binned: bin k of nbins over L_z (centre (k + 1/2) L_z /
 nbins) carries s_a = n_k / (L_x L_y), and xi is the minimum image in z.
+Every molecule of bin b receives the force evaluated at b's centre, so the
+pair of bins (b, k) contributes opposite forces n_b n_k (...) and the
+correction adds no net momentum.
 """
 from __future__ import annotations
 
@@ -48,14 +51,19 @@ def sheet_force(xi, areal, rc, eps=1.0, sigma=1.0):
     return 2.0 * math.pi * areal * xi * 4.0 * eps * (s6 * s6 - s6)
 
 
-def lrc_forces(pos, box, nbins, rc, eps=1.0, sigma=1.0):
-    """z-component of the long-range correction on every molecule and the
-    histogram it is built from."""
-    pos = np.asarray(pos, dtype=np.float64)
+def bin_forces(hist, box, rc, eps=1.0, sigma=1.0):
+    """Correction z-force at each bin centre from the binned profile."""
     lx, ly, lz = (float(b) for b in box)
-    hist = z_histogram(pos, box, nbins)
+    nbins = len(hist)
     centres = (np.arange(nbins) + 0.5) * (lz / nbins)
-    xi = pos[:, 2][:, None] - centres[None, :]
+    xi = centres[:, None] - centres[None, :]
     xi = xi - lz * np.rint(xi / lz)
-    fz = (sheet_force(xi, hist[None, :] / (lx * ly), rc, eps, sigma)).sum(axis=1)
-    return fz, hist
+    return sheet_force(xi, np.asarray(hist, dtype=np.float64)[None, :] / (lx * ly), rc, eps, sigma).sum(axis=1)
+
+
+def lrc_forces(pos, box, nbins, rc, eps=1.0, sigma=1.0):
+    """z-component of the long-range correction on every molecule (the force
+    at its bin's centre) and the histogram it is built from."""
+    k = z_bins(pos, box, nbins)
+    hist = np.bincount(k, minlength=nbins).astype(np.int64)
+    return bin_forces(hist, box, rc, eps, sigma)[k], hist

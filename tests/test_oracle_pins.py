@@ -459,9 +459,10 @@ def test_lrc_vanishes_for_uniform_density_and_flips_under_mirror():
     q = p.copy()
     q[:, 2] = box[2] - p[:, 2]
     fz2, _ = slab.lrc_forces(q, box, 600, 2.5)
-    # bins mirror exactly only when no molecule sits on a bin edge; compare
-    # with the tolerance of one bin width of displacement
-    assert np.allclose(fz2, -fz1, atol=5e-3 * np.abs(fz1).max())
+    # (no molecule sits on a bin edge here, so the bins mirror exactly)
+    assert np.allclose(fz2, -fz1, rtol=0, atol=1e-12 * np.abs(fz1).max())
     # molecules inside the slab near its lower face are pulled up (+z)
     near = (p[:, 2] > 10.5) & (p[:, 2] < 12.0)
     assert (fz1[near] > 0).mean() > 0.9
+    # no net force: bins act on each other with opposite forces
+    assert abs(fz1.sum()) < 1e-12 * np.abs(fz1).sum()
