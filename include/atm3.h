@@ -290,6 +290,28 @@ int atm3_md_kinetic(atm3_ctx* ctx, const double* vel, int64_t n, double* ke_out)
  * finite, dof outside [1, 3n]. */
 int atm3_md_rescale(atm3_ctx* ctx, double* vel, int64_t n, double temperature, int64_t dof);
 
+/* Long-range correction of the LJ forces in planar geometry, for the slab
+ * runs of Sec. 5.2 (the paper adds one and cites it without stating it).
+ * The instantaneous density profile along z is binned into nbins bins over
+ * L_z: a molecule's bin is k = floor(z' * (nbins / L_z)), clamped to
+ * [0, nbins - 1], with z' = z - L_z floor(z / L_z) (FP64, bit-exact).  Each
+ * bin is taken as a uniform sheet of areal density n_k / (L_x L_y) at its
+ * centre.  Its molecules beyond rc pull a molecule at height offset xi
+ * along z with 2 pi s_a xi phi(max(rc, |xi|)), where phi is the LJ
+ * potential 4 eps [(sigma/r)^12 - (sigma/r)^6] and xi the minimum image.
+ * Every molecule of bin b takes the force at b's centre (FP64 sum over the
+ * bins), added in FP64 to forces[3i + 2]; bin pairs act with opposite
+ * forces, so no net momentum is added.
+ *   pos       device, n*3 FP64 positions
+ *   forces    device, n*3 FP32, updated in place (z components)
+ *   hist_sum  device, nbins int64, or NULL: this call's bin counts are added
+ *             (density profile sampling)
+ * Only enqueues.  Errors: ATM3_EINVAL for a NULL pointer, n < 1, a box length
+ * not finite and > 0, nbins outside [1, 4096], rc <= 0 or rc > L_z / 2,
+ * eps or sigma <= 0. */
+int atm3_md_slab_lrc(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], int32_t nbins, double rc,
+                     double eps, double sigma, float* forces, int64_t* hist_sum);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,7 +33,7 @@ EXPORTS = (
     "atm3_mlp_create", "atm3_mlp_destroy", "atm3_mlp_set_params", "atm3_mlp_get_params",
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
-    "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale",
+    "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale", "atm3_md_slab_lrc",
 )
 MLP_NPARAM = 43650
 MLP_NDESC = 64
@@ -138,6 +138,9 @@ def load():
         lib.atm3_md_kinetic.restype = ctypes.c_int
         lib.atm3_md_rescale.argtypes = [vp, vp, i64, ctypes.c_double, i64]
         lib.atm3_md_rescale.restype = ctypes.c_int
+        lib.atm3_md_slab_lrc.argtypes = [vp, vp, i64, dptr, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, vp, vp]
+        lib.atm3_md_slab_lrc.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -244,6 +247,24 @@ class Context:
             self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box), ctypes.byref(params),
             ctypes.c_void_p(forces.data_ptr()), ctypes.c_void_p(result_dev.data_ptr())))
 
+
+    def slab_lrc(self, pos, box, forces, nbins=600, rc=2.5, eps=1.0, sigma=1.0, hist_sum=None):
+        """Add the planar long-range correction of the LJ force to the z
+        components of `forces` (enqueued); `hist_sum` (int64, nbins) gets this
+        configuration's z histogram added."""
+        import torch
+        pos = self._pos(pos)
+        if not (forces.is_cuda and forces.dtype == torch.float32 and forces.is_contiguous()
+                and forces.shape == pos.shape):
+            raise ValueError("forces must be a contiguous float32 device tensor shaped like pos")
+        if hist_sum is not None and not (hist_sum.is_cuda and hist_sum.dtype == torch.int64
+                                         and hist_sum.is_contiguous() and hist_sum.numel() == nbins):
+            raise ValueError("hist_sum must be a contiguous int64 device tensor of nbins entries")
+        self._stream()
+        self._check(self.lib.atm3_md_slab_lrc(self.h, ctypes.c_void_p(pos.data_ptr()), pos.shape[0], _box(box),
+                                              int(nbins), float(rc), float(eps), float(sigma),
+                                              ctypes.c_void_p(forces.data_ptr()),
+                                              None if hist_sum is None else ctypes.c_void_p(hist_sum.data_ptr())))
 
     def profile(self, enable: bool):
         """Start (clearing totals) or stop HIP-event timing of the kernel phases."""
@@ -467,14 +488,17 @@ def md_run(pos, vel, box, steps, dt=0.002, record_every=1, frames=None, **force_
     return out
 
 
-def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, **force_kw):
+def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, profile=None, **force_kw):
     """Velocity Verlet with isokinetic rescaling to `temperature` after every
     step (3N - 3 degrees of freedom), updating the FP64 device tensors `pos`
     and `vel` in place; force_kw go to make_params.  Nothing synchronises with
     the host inside the loop: each sampled step's result struct is written to
     its own device row.  Returns a float64 array (n_samples, 4) with the
     atm3_result fields e_lj, e_atm, w_lj, w_atm at steps sample_every,
-    2 sample_every, ..."""
+    2 sample_every, ...  With lrc_bins > 0 every force evaluation gets the
+    planar long-range correction of the LJ force on that many z bins, and
+    `profile` (int64 device tensor of lrc_bins, if given) accumulates the z
+    histogram of every step."""
     import numpy as np
     import torch
     ctx = context(pos.device)
@@ -489,11 +513,16 @@ def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, **force_kw):
     stride = 128  # bytes per result row (>= sizeof(atm3_result), aligned)
     ns = steps // sample_every
     rows = torch.zeros((ns + 1) * stride, dtype=torch.uint8, device=pos.device)
+    lrc = dict(rc=prm.rc, eps=prm.eps, sigma=prm.sigma)
     ctx.compute_forces_async(pos, box, f, rows[ns * stride:], prm)  # spare row
+    if lrc_bins:
+        ctx.slab_lrc(pos, box, f, lrc_bins, **lrc)
     for k in range(1, steps + 1):
         ctx._check(lib.atm3_md_kick_drift(ctx.h, _ptr(pos), _ptr(vel), _ptr(f), n, float(dt)))
         row = (k // sample_every - 1) if k % sample_every == 0 else ns
         ctx.compute_forces_async(pos, box, f, rows[row * stride:], prm)
+        if lrc_bins:
+            ctx.slab_lrc(pos, box, f, lrc_bins, hist_sum=profile, **lrc)
         ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
         ctx._check(lib.atm3_md_rescale(ctx.h, _ptr(vel), n, float(temperature), 3 * n - 3))
     torch.cuda.synchronize(pos.device)

@@ -69,6 +69,7 @@ enum Buf {
   B_TDA,          // float [N][128] dL/dA
   B_TDAB,         // bf16 [N][128]
   B_TPART,        // float split-K partial products
+  B_ZHIST,        // uint32 [nbins] z histogram of the slab correction
   B_NBUF
 };
 

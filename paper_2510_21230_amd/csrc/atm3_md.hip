@@ -57,6 +57,75 @@ __global__ __launch_bounds__(256) void k_rescale(double* __restrict__ v, int64_t
   if (k > 0.0) v[i] = v[i] * sqrt(ke_target / k);
 }
 
+// Planar long-range correction of the LJ force (the slab runs of Sec. 5.2
+// add one and cite it without stating it).  A sheet of areal density s_a at
+// height offset xi pulls a molecule, through its molecules beyond rc, with
+// F_z = 2 pi s_a xi phi(max(rc, |xi|)), phi the LJ potential; the sheets
+// are the bins of the instantaneous z histogram, and every molecule of a bin
+// takes the force at the bin's centre (bin pairs act with opposite forces:
+// no net momentum).
+constexpr int LRC_MAXBINS = 4096;
+
+__global__ void k_zero_u32(uint32_t* p, int32_t m) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// z <- z - L_z floor(z / L_z), k = floor(z * (nbins / L_z)) clamped (FP64,
+// no contraction: the bin is bit-exact).
+__device__ __forceinline__ int zbin(double z, double lz, double inv, int nbins) {
+#pragma clang fp contract(off)
+  z = z - lz * floor(z / lz);
+  const int k = (int)floor(z * inv);
+  return k < 0 ? 0 : (k >= nbins ? nbins - 1 : k);
+}
+
+__global__ __launch_bounds__(256) void k_zhist(const double* __restrict__ pos, int64_t n, double lz, double inv,
+                                               int32_t nbins, uint32_t* __restrict__ hist) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  atomicAdd(&hist[zbin(pos[3 * i + 2], lz, inv, nbins)], 1u);
+}
+
+struct LrcArgs {
+  const double* pos;
+  int64_t n;
+  const uint32_t* hist;
+  double* fbin;  // [nbins] force at each bin centre
+  int32_t nbins;
+  double lz, inv, dz, coef, rc, sigma, eps4;  // coef = 2 pi / (L_x L_y)
+  float* forces;
+  long long* hist_sum;
+};
+
+// Force at each bin centre (one thread per bin, fixed order over the bins);
+// the histogram sums for profile sampling.
+__global__ __launch_bounds__(256) void k_lrc_bins(LrcArgs a) {
+  __shared__ double sh[LRC_MAXBINS];
+  for (int k = threadIdx.x; k < a.nbins; k += blockDim.x) sh[k] = (double)a.hist[k];
+  __syncthreads();
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.nbins) return;
+  if (a.hist_sum) a.hist_sum[b] += (long long)a.hist[b];
+  const double zb = (b + 0.5) * a.dz;
+  double f = 0.0;
+  for (int k = 0; k < a.nbins; ++k) {
+    if (sh[k] == 0.0) continue;
+    double xi = zb - (k + 0.5) * a.dz;
+    xi -= a.lz * rint(xi / a.lz);
+    const double r = fmax(a.rc, fabs(xi));
+    const double s2 = (a.sigma / r) * (a.sigma / r), s6 = s2 * s2 * s2;
+    f += sh[k] * xi * (a.eps4 * (s6 * s6 - s6));
+  }
+  a.fbin[b] = a.coef * f;
+}
+
+__global__ __launch_bounds__(256) void k_lrc_apply(LrcArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int b = zbin(a.pos[3 * i + 2], a.lz, a.inv, a.nbins);
+  a.forces[3 * i + 2] = (float)((double)a.forces[3 * i + 2] + a.fbin[b]);
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 int md_check(atm3_ctx* ctx, const void* a, const void* b, int64_t n, double dt) {
@@ -131,6 +200,46 @@ int atm3_md_rescale(atm3_ctx* ctx, double* vel, int64_t n, double temperature, i
                      0.5 * (double)dof * temperature);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "rescale launch");
+  return ATM3_OK;
+}
+
+int atm3_md_slab_lrc(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], int32_t nbins, double rc,
+                     double eps, double sigma, float* forces, int64_t* hist_sum) {
+  int r = md_check(ctx, pos, forces, n, 1.0);
+  if (r) return r;
+  if (!box) return fail(ctx, ATM3_EINVAL, "box is NULL");
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] > 0.0) || !isfinite(box[d])) return fail(ctx, ATM3_EINVAL, "box lengths must be finite and > 0");
+  if (nbins < 1 || nbins > LRC_MAXBINS) return fail(ctx, ATM3_EINVAL, "nbins must be in [1, 4096]");
+  if (!(rc > 0.0) || !(2.0 * rc <= box[2])) return fail(ctx, ATM3_EINVAL, "rc must be > 0 and at most L_z / 2");
+  if (!(eps > 0.0) || !(sigma > 0.0)) return fail(ctx, ATM3_EINVAL, "eps and sigma must be > 0");
+  // histogram (uint32) and bin forces (FP64) in one scratch buffer
+  if ((r = ensure(ctx, B_ZHIST, 12 * (size_t)nbins + 16))) return r;
+  uint32_t* hist = (uint32_t*)ctx->s.p[B_ZHIST];
+  double* fbin = (double*)((char*)ctx->s.p[B_ZHIST] + ((4 * (size_t)nbins + 15) & ~(size_t)15));
+  const double inv = (double)nbins / box[2];
+  hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nbins, 256)), dim3(256), 0, ctx->stream, hist, nbins);
+  hipLaunchKernelGGL(k_zhist, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, pos, n, box[2], inv, nbins,
+                     hist);
+  LrcArgs a;
+  a.pos = pos;
+  a.n = n;
+  a.hist = hist;
+  a.fbin = fbin;
+  a.nbins = nbins;
+  a.lz = box[2];
+  a.inv = inv;
+  a.dz = box[2] / nbins;
+  a.coef = 2.0 * M_PI / (box[0] * box[1]);
+  a.rc = rc;
+  a.sigma = sigma;
+  a.eps4 = 4.0 * eps;
+  a.forces = forces;
+  a.hist_sum = (long long*)hist_sum;
+  hipLaunchKernelGGL(k_lrc_bins, dim3(blocks_for(nbins, 256)), dim3(256), 0, ctx->stream, a);
+  hipLaunchKernelGGL(k_lrc_apply, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(ctx, e, "slab correction launch");
   return ATM3_OK;
 }
 

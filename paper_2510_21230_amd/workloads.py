@@ -66,6 +66,37 @@ def sc(n: int, side: float, seed: int = SEED_BASE + 9):
     return np.ascontiguousarray(sites), np.array([side, side, side])
 
 
+def fcc_box(n: int, box, seed: int = SEED_BASE + 11):
+    """n molecules on an FCC lattice filling an orthorhombic box: nc_d =
+    ceil(L_d / a) unit cells along each side for a = (4 V / n)^(1/3),
+    cell edges L_d / nc_d, n of the sites kept by a seeded permutation."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    a = (4.0 * float(np.prod(box)) / n) ** (1.0 / 3.0)
+    nc = [int(math.ceil(L / a - 1e-9)) for L in box]
+    sites = fcc_sites(nc[0], nc[1], nc[2], tuple(L / k for L, k in zip(box, nc))) + 0.25 * box / np.array(nc)
+    if len(sites) > n:
+        sites = sites[np.sort(rng.permutation(len(sites))[:n])]
+    return np.ascontiguousarray(sites), box.copy()
+
+
+def lattice(n: int, box, seed: int = SEED_BASE + 10):
+    """n molecules on a simple orthorhombic lattice filling an orthorhombic
+    box (the homogeneous start of the slab runs of Sec. 5.2): k_d =
+    ceil(L_d / a) sites along each side for a = (V / n)^(1/3), spacing
+    L_d / k_d, n of the sites kept by a seeded permutation."""
+    rng = np.random.default_rng(seed)
+    box = np.asarray(box, dtype=np.float64)
+    a = (float(np.prod(box)) / n) ** (1.0 / 3.0)
+    k = [int(math.ceil(L / a - 1e-9)) for L in box]
+    g = [(np.arange(kd) + 0.5) * (L / kd) for kd, L in zip(k, box)]
+    x, y, z = np.meshgrid(*g, indexing="ij")
+    sites = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    if len(sites) > n:
+        sites = sites[np.sort(rng.permutation(len(sites))[:n])]
+    return np.ascontiguousarray(sites), box.copy()
+
+
 def uniform(n: int, box, seed: int = SEED_BASE + 7):
     """n molecules uniformly at random in an orthorhombic box."""
     rng = np.random.default_rng(seed)

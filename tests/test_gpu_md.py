@@ -96,3 +96,50 @@ def test_rescale_sets_kinetic_energy(torch_cuda):
     assert np.allclose(lam, lam.flat[0], rtol=1e-12)
     for T, dof in [(0.0, 3 * n - 3), (-1.0, 3), (float("nan"), 3), (1.0, 0), (1.0, 3 * n + 1)]:
         assert ctx.lib.atm3_md_rescale(ctx.h, _lib._ptr(v), n, T, dof) == -1
+
+
+def test_slab_correction_matches_oracle(torch_cuda):
+    """atm3_md_slab_lrc: the z histogram bit for bit and the z-force of the
+    planar LJ long-range correction within 3e-6 of the FP64 oracle, on a
+    liquid slab with vapour (600 bins over L_z = 75, the paper's slab box);
+    x and y untouched; the histogram accumulates over calls; invalid
+    arguments are ATM3_EINVAL."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    from oracle import slab
+    box = np.array([12.5, 12.5, 75.0])
+    liq, _ = workloads.rsa(2600, box, dmin=0.85, lo=np.array([0.0, 0.0, 25.0]), hi=np.array([12.5, 12.5, 50.0]),
+                           seed=workloads.SEED_BASE + 63)
+    gas, _ = workloads.rsa(60, box, dmin=0.85, lo=np.array([0.0, 0.0, 55.0]), hi=np.array([12.5, 12.5, 95.0]),
+                           seed=workloads.SEED_BASE + 64)
+    pos = np.concatenate([liq, gas])  # the vapour band crosses the periodic boundary in z
+    n = len(pos)
+    _say(f"[slab lrc] n={n}")
+    fz_ref, hist_ref = slab.lrc_forces(pos, box, 600, 2.5)
+    ctx = atm3.context(0)
+    p = torch.from_numpy(pos).cuda()
+    f0 = np.random.default_rng(3).normal(size=(n, 3)).astype(np.float32)
+    f = torch.from_numpy(f0.copy()).cuda()
+    h = torch.zeros(600, dtype=torch.int64, device="cuda")
+    ctx.slab_lrc(p, box, f, 600, rc=2.5, hist_sum=h)
+    ctx.slab_lrc(p, box, torch.zeros_like(f), 600, rc=2.5, hist_sum=h)
+    torch.cuda.synchronize()
+    got = f.cpu().numpy()
+    assert (h.cpu().numpy() == 2 * hist_ref).all()
+    assert (got[:, :2] == f0[:, :2]).all()
+    dz = got[:, 2].astype(np.float64) - f0[:, 2].astype(np.float64)
+    scale = np.abs(fz_ref).max()
+    assert scale > 0.1
+    err = np.abs(dz - fz_ref).max() / scale
+    _say(f"  max |F_z| {scale:.3f}, max error {err:.2e}")
+    # FP64 sums; the one FP32 rounding of the updated force (|f| up to about
+    # 4 here) is 2.4e-7 absolute, under 1e-6 of the largest correction
+    assert err < 3e-6
+    # molecules just inside the liquid's faces are pulled into the liquid
+    assert (fz_ref[(pos[:, 2] > 25.2) & (pos[:, 2] < 26.5)] > 0).mean() > 0.9
+    assert (fz_ref[(pos[:, 2] > 48.5) & (pos[:, 2] < 49.8)] < 0).mean() > 0.9
+    for args in [dict(nbins=0), dict(nbins=5000), dict(rc=40.0), dict(rc=-1.0), dict(eps=0.0)]:
+        kw = dict(nbins=600, rc=2.5, eps=1.0, sigma=1.0)
+        kw.update(args)
+        with pytest.raises(ValueError):
+            ctx.slab_lrc(p, box, f, **kw)

@@ -27,3 +27,29 @@ def test_maxwell_has_zero_momentum_and_exact_temperature():
     v = workloads.maxwell(1000, 0.746)
     assert np.abs(v.sum(axis=0)).max() < 1e-12
     assert abs((v * v).sum() / (3 * 1000 - 3) - 0.746) < 1e-12
+
+
+def test_lattice_start_of_the_slab_runs():
+    box = np.array([12.5, 12.5, 25.0])
+    pos, b = workloads.lattice(3800, box)
+    assert pos.shape == (3800, 3) and np.all(b == box)
+    assert np.all((pos > 0) & (pos < box))
+    d = pos[:, None, :] - pos[None, :, :]
+    d -= box * np.rint(d / box)
+    r2 = (d ** 2).sum(-1) + np.eye(len(pos)) * 1e9
+    assert np.sqrt(r2.min()) > 0.95  # spacings 12.5/13 and 25/26
+    assert len({tuple(np.round(r, 9)) for r in pos}) == 3800
+    assert np.array_equal(pos, workloads.lattice(3800, box)[0])
+
+
+def test_fcc_box_start_of_the_slab_runs():
+    box = np.array([12.5, 12.5, 25.0])
+    pos, b = workloads.fcc_box(3800, box)
+    assert pos.shape == (3800, 3) and np.all(b == box)
+    assert np.all((pos > 0) & (pos < box))
+    d = pos[:, None, :] - pos[None, :, :]
+    d -= box * np.rint(d / box)
+    r2 = (d ** 2).sum(-1) + np.eye(len(pos)) * 1e9
+    # 8 x 8 x 16 cells of edge 1.5625: nearest neighbours at a / sqrt(2)
+    assert abs(np.sqrt(r2.min()) - 1.5625 / np.sqrt(2)) < 1e-12
+    assert np.array_equal(pos, workloads.fcc_box(3800, box)[0])
