@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // item counts of dense liquids (about 0.8 and above); what still does not
 // fit is queued (defer[ncells + 2..]) for k_block_big.
 template <int PCAP, int KCAP>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_block_wide(ForceArgs a) {
+__global__ __launch_bounds__(WG) void k_block_wide(ForceArgs a) {
   __shared__ LdsFast<PCAP, KCAP> L;
   int32_t* q2 = a.defer + 2 + a.ncells;
   const int nq = a.defer[0];
