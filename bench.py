@@ -174,6 +174,13 @@ def rc_study(args):
                 ("exact product rule 3c08", lambda: ctx.compute_forces(pos, box, forces, rc=rc, nu=0.073,
                                                                      truncation="product")),
                 ("LJ + surrogate", lambda: mlp.forces(pos, box, rc=rc, nu=0.073, forces=forces))]
+        if args.study_variants:
+            for var in ["3c18", "3c01"]:
+                runs.append((f"exact pair rule {var}",
+                             lambda var=var: ctx.compute_forces(pos, box, forces, rc=rc, nu=0.073, variant=var)))
+                runs.append((f"exact product rule {var}",
+                             lambda var=var: ctx.compute_forces(pos, box, forces, rc=rc, nu=0.073,
+                                                                truncation="product", variant=var)))
         for name, fn in runs:
             for _ in range(args.warmup):
                 out = fn()
@@ -204,6 +211,8 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--study-rc", default="",
                     help="comma-separated cutoffs: print the cost-against-rc study instead of the benchmark line")
+    ap.add_argument("--study-variants", action="store_true",
+                    help="with --study-rc: also time the 3c18 and 3c01 cell sets under both rules")
     args = ap.parse_args()
     if args.study_rc:
         rc_study(args)
