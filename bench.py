@@ -91,28 +91,35 @@ def cpu_baseline(pos, box, params, budget_s=15.0):
 
 def surrogate_leg(pos, box, f_exact, params, args):
     """Train the learned pair surrogate on the GPU on exact ATM forces that
-    the exact kernel generates for the two smaller workloads: the N=1,000
-    jittered FCC at density 0.6, and frames every 10 steps of a 100-step
+    the exact kernel generates for smaller systems: the N=1,000 jittered FCC
+    at density 0.6; 100 frames, every 10 steps, of a 1,000-step
     velocity-Verlet run of N=32,000 (FCC 20^3, density 0.7, Maxwell T=1.0,
-    dt=0.002).  Then time it on the benchmark system and measure its force
-    error against the exact LJ + ATM forces computed above."""
+    dt=0.002); and 20 frames of a 200-step run of the same size at density
+    0.75, the benchmark's density.  Then time it on the benchmark system
+    (another configuration) and measure its force error against the exact
+    LJ + ATM forces computed above."""
     import torch
 
     import paper_2510_21230_amd as atm3
     from paper_2510_21230_amd import workloads
 
     dev = pos.device
+
+    def md_frames(rho, steps, seed):
+        p2, b2 = workloads.fcc(32000, rho, jitter=0.0, seed=seed)
+        v2 = torch.from_numpy(workloads.maxwell(32000, 1.0, seed=seed + 1)).to(dev)
+        p2 = torch.from_numpy(p2).to(dev)
+        traj = []
+        atm3.md_run(p2, v2, b2, steps, dt=0.002, record_every=10, frames=traj, **params)
+        return [(fpos, b2, atm3.compute_forces(fpos, b2, nu=params["nu"], terms=atm3.TERM_ATM)[0])
+                for fpos, _ in traj[1:]]
+
     frames = []
     p1, b1 = workloads.make("fcc1k")
     p1 = torch.from_numpy(p1).to(dev)
     frames.append((p1, b1, atm3.compute_forces(p1, b1, nu=params["nu"], terms=atm3.TERM_ATM)[0]))
-    p2, b2 = workloads.fcc(32000, 0.7, jitter=0.0, seed=workloads.SEED_BASE + 2)
-    v2 = torch.from_numpy(workloads.maxwell(32000, 1.0, seed=workloads.SEED_BASE + 3)).to(dev)
-    p2 = torch.from_numpy(p2).to(dev)
-    traj = []
-    atm3.md_run(p2, v2, b2, 100, dt=0.002, record_every=10, frames=traj, **params)
-    for fpos, _ in traj[1:]:
-        frames.append((fpos, b2, atm3.compute_forces(fpos, b2, nu=params["nu"], terms=atm3.TERM_ATM)[0]))
+    frames += md_frames(0.7, 1000, workloads.SEED_BASE + 2)
+    frames += md_frames(0.75, 200, workloads.SEED_BASE + 20)
     mlp = atm3.Mlp(seed=3)
     mlp.fit_stats(frames[-1][0], frames[-1][1])
     torch.cuda.synchronize()
@@ -204,7 +211,7 @@ def main():
     ap.add_argument("--workload", default="fcc1m", choices=["fcc1m", "fcc32k", "fcc1k", "slab20k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--surrogate-train-steps", type=int, default=1500,
+    ap.add_argument("--surrogate-train-steps", type=int, default=3000,
                     help="training steps of the surrogate before its timing (0: skip the surrogate leg)")
     ap.add_argument("--surrogate-steps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
