@@ -139,7 +139,8 @@ def surrogate_leg(pos, box, f_exact, params, args):
     out = {"train_steps": args.surrogate_train_steps, "train_seconds": t_train, "train_frames": len(frames),
            "train_loss_first": losses[0], "train_loss_last": float(sum(losses[-20:]) / min(20, len(losses))),
            "force_rms_error_lj_only": e_lj, "force_rms_exact": rms(torch.zeros_like(f_exact))}
-    for tag, thr in (("fallback_1e-3", 1e-3), ("no_fallback", float("inf"))):
+    for tag, thr in (("fallback_1e-3", 1e-3), ("fallback_1e-2", 1e-2), ("fallback_3e-2", 3e-2),
+                     ("no_fallback", float("inf"))):
         f_s = torch.empty_like(f_exact)
         mlp.forces(pos, box, threshold=thr, forces=f_s, **params)
         torch.cuda.synchronize()
