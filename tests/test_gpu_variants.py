@@ -84,3 +84,29 @@ def test_small_boxes_are_rejected(torch_cuda):
         atm3.compute_forces(p, box, variant="3c18")  # 4 cells < 5
     with pytest.raises(ValueError, match="box too small"):
         atm3.compute_forces(p, box, variant="3c18", truncation="product")
+
+
+@pytest.mark.parametrize("k", range(9))
+def test_fuzz_product_rule(torch_cuda, orc, k):
+    """Seeded orthorhombic boxes of 3-7 cells per dimension (5-7 for 3c18),
+    molecules at least 0.8 sigma apart, every cell set under the product
+    rule: counts exact, forces and energies as above."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    var = ["3c08", "3c18", "3c01"][k % 3]
+    rng = np.random.default_rng(4200 + k)
+    lo = 12.6 if var == "3c18" else 7.6
+    box = rng.uniform(lo, 18.0, 3)
+    n = int(rng.integers(100, int(min(1200, 0.5 * np.prod(box)))))
+    pos, _ = workloads.rsa(n, box, 0.8, seed=4300 + k)
+    _say(f"[fuzz product {var}] k={k} n={len(pos)} box={np.round(box, 2)}")
+    ref = orc.brute(pos, box, rc=RC, nu=NU, truncation="product", variant=var)
+    f, r = atm3.compute_forces(torch.from_numpy(pos).cuda(), box, nu=NU, truncation="product", variant=var)
+    torch.cuda.synchronize()
+    assert r["n_pairs"] == ref.n_pairs
+    assert r["n_triplets"] == ref.n_triplets
+    assert r["n_candidates"] == ref.n_candidates
+    assert force_err(f.cpu().numpy().astype(np.float64), ref.forces) <= 1e-5
+    assert r["e_atm"] == pytest.approx(ref.e_atm, rel=1e-6)
+    assert r["w_atm"] == pytest.approx(ref.w_atm, rel=1e-6)
+    assert r["e_lj"] == pytest.approx(ref.e_lj, rel=1e-6)
