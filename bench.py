@@ -204,6 +204,52 @@ def rc_study(args):
                               "n_pairs": r["n_pairs"], "n_triplets": r["n_triplets"]}), flush=True)
 
 
+def paper_study(args):
+    """The paper's traversal benchmark workload (Sec. 5.3): N = 37,000 on a
+    simple cubic lattice in a periodic box of side 37.5 (15^3 cells at
+    rc = 2.5), not equilibrated, 10 iterations of the three-body forces
+    (the paper times the three-body part only), for each cell set and
+    cutoff rule.  Prints one JSON line per combination: the mean time per
+    evaluation over `--steps` iterations after `--warmup`, and MMUPS =
+    N * iterations / (T * 10^6) (eq. mmups)."""
+    import torch
+
+    import paper_2510_21230_amd as atm3
+    from paper_2510_21230_amd import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    pos_np, box = workloads.sc(37000, 37.5)
+    pos = torch.from_numpy(pos_np).to(dev)
+    n = len(pos_np)
+    ctx = atm3.context(0)
+    forces = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    res = torch.zeros(128, dtype=torch.uint8, device=dev)
+    for var in ["3c01", "3c18", "3c08"]:
+        for trunc in ["product", "pair"]:
+            p = atm3.make_params(rc=2.5, nu=0.073, truncation=trunc, variant=var, terms=atm3.TERM_ATM)
+            for _ in range(args.warmup):
+                ctx.compute_forces_async(pos, box, forces, res, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.compute_forces_async(pos, box, forces, res, p)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) / args.steps
+            r = _lib_result(res)
+            if r["status"] != 0:
+                raise SystemExit(f"{var} {trunc}: status {r['status']}")
+            print(json.dumps({"study": "paper traversal workload", "n": n, "box": 37.5, "variant": var,
+                              "truncation": trunc, "terms": "ATM", "ms_per_evaluation": t * 1e3,
+                              "mmups": n / t / 1e6, "n_triplets": r["n_triplets"],
+                              "n_candidates": r["n_candidates"]}), flush=True)
+
+
+def _lib_result(res):
+    from paper_2510_21230_amd import _lib
+    return _lib.result_from_bytes(res.cpu().numpy().tobytes())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +267,12 @@ def main():
                     help="comma-separated cutoffs: print the cost-against-rc study instead of the benchmark line")
     ap.add_argument("--study-variants", action="store_true",
                     help="with --study-rc: also time the 3c18 and 3c01 cell sets under both rules")
+    ap.add_argument("--study-paper", action="store_true",
+                    help="print the paper's traversal-benchmark workload (N=37,000) for every cell set and rule")
     args = ap.parse_args()
+    if args.study_paper:
+        paper_study(args)
+        return
     if args.study_rc:
         rc_study(args)
         return
