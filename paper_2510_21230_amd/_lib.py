@@ -34,6 +34,7 @@ EXPORTS = (
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
     "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale", "atm3_md_slab_lrc",
+    "atm3_md_nvt_graph",
 )
 MLP_NPARAM = 43650
 MLP_NDESC = 64
@@ -141,6 +142,9 @@ def load():
         lib.atm3_md_slab_lrc.argtypes = [vp, vp, i64, dptr, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, vp, vp]
         lib.atm3_md_slab_lrc.restype = ctypes.c_int
+        lib.atm3_md_nvt_graph.argtypes = [vp, vp, vp, i64, dptr, ctypes.POINTER(Params), i64, ctypes.c_double,
+                                          ctypes.c_double, i64, i64, vp, vp, i64, ctypes.c_int32, vp]
+        lib.atm3_md_nvt_graph.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -488,7 +492,8 @@ def md_run(pos, vel, box, steps, dt=0.002, record_every=1, frames=None, **force_
     return out
 
 
-def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, profile=None, **force_kw):
+def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, profile=None, graph=False,
+           **force_kw):
     """Velocity Verlet with isokinetic rescaling to `temperature` after every
     step (3N - 3 degrees of freedom), updating the FP64 device tensors `pos`
     and `vel` in place; force_kw go to make_params.  Nothing synchronises with
@@ -498,8 +503,9 @@ def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, pr
     2 sample_every, ...  With lrc_bins > 0 every force evaluation gets the
     planar long-range correction of the LJ force on that many z bins, and
     `profile` (int64 device tensor of lrc_bins, if given) accumulates the z
-    histogram of every step."""
-    import numpy as np
+    histogram of every step.  With graph=True one step is captured as a HIP
+    graph and launched `steps` times (atm3_md_nvt_graph): same trajectory
+    and results, without the per-step host launches."""
     import torch
     ctx = context(pos.device)
     lib = ctx.lib
@@ -514,6 +520,16 @@ def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, pr
     ns = steps // sample_every
     rows = torch.zeros((ns + 1) * stride, dtype=torch.uint8, device=pos.device)
     lrc = dict(rc=prm.rc, eps=prm.eps, sigma=prm.sigma)
+    if profile is not None and not (profile.is_cuda and profile.dtype == torch.int64 and profile.is_contiguous()
+                                    and profile.numel() == lrc_bins):
+        raise ValueError("profile must be a contiguous int64 device tensor of lrc_bins entries")
+    if graph:
+        ctx._stream()
+        ctx._check(lib.atm3_md_nvt_graph(ctx.h, _ptr(pos), _ptr(vel), n, _box(box), ctypes.byref(prm), int(steps),
+                                         float(dt), float(temperature), 3 * n - 3, int(sample_every), _ptr(f),
+                                         _ptr(rows), stride, int(lrc_bins),
+                                         None if profile is None else _ptr(profile)))
+        return _rows_out(rows, ns, stride)
     ctx.compute_forces_async(pos, box, f, rows[ns * stride:], prm)  # spare row
     if lrc_bins:
         ctx.slab_lrc(pos, box, f, lrc_bins, **lrc)
@@ -525,7 +541,15 @@ def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, pr
             ctx.slab_lrc(pos, box, f, lrc_bins, hist_sum=profile, **lrc)
         ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
         ctx._check(lib.atm3_md_rescale(ctx.h, _ptr(vel), n, float(temperature), 3 * n - 3))
-    torch.cuda.synchronize(pos.device)
+    return _rows_out(rows, ns, stride)
+
+
+def _rows_out(rows, ns, stride):
+    """(ns, 4) e_lj, e_atm, w_lj, w_atm of the result rows; raises on a failed
+    evaluation."""
+    import numpy as np
+    import torch
+    torch.cuda.synchronize(rows.device)
     host = rows.cpu().numpy()
     out = np.zeros((ns, 4))
     for q in range(ns):

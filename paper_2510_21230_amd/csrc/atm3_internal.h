@@ -70,6 +70,7 @@ enum Buf {
   B_TDAB,         // bf16 [N][128]
   B_TPART,        // float split-K partial products
   B_ZHIST,        // uint32 [nbins] z histogram of the slab correction
+  B_MDSLOT,       // atm3_result of the step in flight + step counter (graph-launched MD)
   B_NBUF
 };
 

@@ -126,6 +126,23 @@ __global__ __launch_bounds__(256) void k_lrc_apply(LrcArgs a) {
   a.forces[3 * i + 2] = (float)((double)a.forces[3 * i + 2] + a.fbin[b]);
 }
 
+// Step counter of a graph-launched run: the result of every sample_every-th
+// step goes to its row (the graph's kernels take fixed arguments, so the row
+// is chosen on the device).
+__global__ void k_md_store(const uint64_t* __restrict__ slot, uint8_t* __restrict__ rows, int64_t stride,
+                           int64_t* __restrict__ ctr, int64_t sample_every, int64_t nsamp) {
+  __shared__ int64_t c;
+  if (threadIdx.x == 0) c = ++ctr[0];
+  __syncthreads();
+  if (c % sample_every != 0 || c / sample_every > nsamp) return;
+  uint64_t* dst = (uint64_t*)(rows + (c / sample_every - 1) * stride);
+  for (int k = threadIdx.x; k < (int)(sizeof(atm3_result) / 8); k += blockDim.x) dst[k] = slot[k];
+}
+
+__global__ void k_zero_i64(int64_t* p) {
+  if (threadIdx.x == 0) p[0] = 0;
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 int md_check(atm3_ctx* ctx, const void* a, const void* b, int64_t n, double dt) {
@@ -240,6 +257,78 @@ int atm3_md_slab_lrc(atm3_ctx* ctx, const double* pos, int64_t n, const double b
   hipLaunchKernelGGL(k_lrc_apply, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(ctx, e, "slab correction launch");
+  return ATM3_OK;
+}
+
+int atm3_md_nvt_graph(atm3_ctx* ctx, double* pos, double* vel, int64_t n, const double box[3],
+                      const atm3_params* params, int64_t steps, double dt, double temperature, int64_t dof,
+                      int64_t sample_every, float* forces, void* rows, int64_t row_stride, int32_t lrc_bins,
+                      int64_t* profile) {
+  static_assert(sizeof(atm3_result) % 8 == 0, "result rows are copied in 8-byte words");
+  int r = md_check(ctx, pos, vel, n, dt);
+  if (r) return r;
+  if (!params || !box || !forces || !rows) return fail(ctx, ATM3_EINVAL, "NULL argument");
+  if (steps < 1 || sample_every < 1) return fail(ctx, ATM3_EINVAL, "steps and sample_every must be >= 1");
+  if (row_stride < (int64_t)sizeof(atm3_result) || row_stride % 8)
+    return fail(ctx, ATM3_EINVAL, "row_stride must be a multiple of 8 of at least sizeof(atm3_result)");
+  if (params->flags & ATM3_FLAG_CHECK_FINITE) return fail(ctx, ATM3_EINVAL, "the finite check cannot be captured");
+  if (ctx->profile) return fail(ctx, ATM3_EINVAL, "phase profiling cannot be captured");
+  if (!(temperature > 0.0) || !isfinite(temperature)) return fail(ctx, ATM3_EINVAL, "temperature must be > 0");
+  if (dof < 1 || dof > 3 * n) return fail(ctx, ATM3_EINVAL, "dof must be in [1, 3n]");
+  if ((r = ensure(ctx, B_MDSLOT, sizeof(atm3_result) + 64))) return r;
+  atm3_result* slot = (atm3_result*)ctx->s.p[B_MDSLOT];
+  int64_t* ctr = (int64_t*)((char*)ctx->s.p[B_MDSLOT] + ((sizeof(atm3_result) + 15) & ~(size_t)15));
+  // every scratch buffer a step uses is sized before the capture (no
+  // allocation or synchronisation may happen inside it): the initial forces,
+  // and the kinetic-energy partials of the thermostat
+  if ((r = atm3_compute_forces_async(ctx, pos, n, box, params, forces, slot))) return r;
+  if (lrc_bins && (r = atm3_md_slab_lrc(ctx, pos, n, box, lrc_bins, params->rc, params->eps, params->sigma,
+                                         forces, nullptr)))
+    return r;
+  const int np = (int)((3 * n + KE_CHUNK - 1) / KE_CHUNK);
+  if ((r = ensure(ctx, B_SRED, 8 * (size_t)np + 64))) return r;
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, ctx->stream, ctr);
+
+  hipStream_t user = ctx->stream, s = nullptr;
+  hipEvent_t e0 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&e0, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(e0, user);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, e0, 0);
+  if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    ctx->stream = s;
+    const int64_t nsamp = steps / sample_every;
+    r = atm3_md_kick_drift(ctx, pos, vel, forces, n, dt);
+    if (!r) r = atm3_compute_forces_async(ctx, pos, n, box, params, forces, slot);
+    if (!r && lrc_bins)
+      r = atm3_md_slab_lrc(ctx, pos, n, box, lrc_bins, params->rc, params->eps, params->sigma, forces, profile);
+    if (!r) r = atm3_md_kick(ctx, vel, forces, n, dt);
+    if (!r) r = atm3_md_rescale(ctx, vel, n, temperature, dof);
+    if (!r) {
+      hipLaunchKernelGGL(k_md_store, dim3(1), dim3(64), 0, s, (const uint64_t*)slot, (uint8_t*)rows, row_stride, ctr,
+                         sample_every, nsamp);
+      e = hipGetLastError();
+    }
+    ctx->stream = user;
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = ec;
+  }
+  if (!r && e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  for (int64_t k = 0; !r && e == hipSuccess && k < steps; ++k) e = hipGraphLaunch(exec, s);
+  if (s) {
+    hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e0) (void)hipEventDestroy(e0);
+  if (s) (void)hipStreamDestroy(s);
+  ctx->stream = user;
+  if (r) return r;
+  if (e != hipSuccess) return hip_fail(ctx, e, "graph-launched MD");
   return ATM3_OK;
 }
 
