@@ -41,7 +41,8 @@ extern "C" {
 #define ATM3_EINVAL (-1)    /* invalid argument (message says which)          */
 #define ATM3_EDEVICE (-2)   /* HIP runtime error or bad device ordinal        */
 #define ATM3_ENOMEM (-3)    /* device allocation failed                       */
-#define ATM3_ERANGE (-4)    /* non-finite input, or a force beyond +-2^31     */
+#define ATM3_ERANGE (-4)    /* non-finite input, or a force term beyond the
+                               fixed-point range (see atm3_compute_forces)   */
 #define ATM3_EOVERFLOW (-5) /* too many molecules in a cell neighbourhood   */
 
 /* Truncation conditions of Sec. 2. */
@@ -50,7 +51,8 @@ extern "C" {
 
 /* Cell sets visited (Sec. 4). */
 #define ATM3_VARIANT_3C08 0 /* cells of one 2x2x2 block, each triplet once       */
-#define ATM3_VARIANT_3C18 1 /* base cell + two of its 13 forward neighbours      */
+#define ATM3_VARIANT_3C18 1 /* base cell + two cells of base or its 13 forward
+                               neighbours                                      */
 #define ATM3_VARIANT_3C01 2 /* per molecule, 27-cell neighbourhood, no Newton 3  */
 
 /* Terms. */
