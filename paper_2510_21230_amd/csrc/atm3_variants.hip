@@ -829,8 +829,13 @@ namespace {
 OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p, int terms,
                  float* forces, int* groups_out, bool* wv, bool* wj) {
   OneArgs a;
+  // blocks per cell: about one group of OS_MOLS molecules each; for LJ alone
+  // (little work per molecule) the staged neighbourhood is shared by the
+  // whole cell, one block per cell once the grid fills the GPU
   const int64_t per_cell = (n + g.ncells - 1) / g.ncells;
-  const int groups = (int)std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
+  int64_t groups64 = std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
+  if (!(terms & ATM3_TERM_ATM)) groups64 = std::min<int64_t>(groups64, (2048 + g.ncells - 1) / g.ncells);
+  const int groups = (int)groups64;
   a.sorted = (const double4*)ctx->s.p[B_SORTED];
   a.start = (const int32_t*)ctx->s.p[B_START];
   a.pos = pos;

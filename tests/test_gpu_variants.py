@@ -110,3 +110,26 @@ def test_fuzz_product_rule(torch_cuda, orc, k):
     assert r["e_atm"] == pytest.approx(ref.e_atm, rel=1e-6)
     assert r["w_atm"] == pytest.approx(ref.w_atm, rel=1e-6)
     assert r["e_lj"] == pytest.approx(ref.e_lj, rel=1e-6)
+
+
+@pytest.mark.parametrize("var", ["3c08", "3c18", "3c01"])
+def test_product_rule_fcc32k_sampled(torch_cuda, orc, var):
+    """The product rule on fcc32k (14^3 cells: one one-sided block per cell
+    for the LJ part, one block-kernel block per base cell): forces of 200
+    sampled molecules against the per-molecule oracle, and the LJ pairs,
+    energy and virial equal to the pairwise-cutoff path's."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    pos, box = workloads.make("fcc32k")
+    p = torch.from_numpy(pos).cuda()
+    _say(f"[product fcc32k {var}]")
+    f, r = atm3.compute_forces(p, box, nu=NU, truncation="product", variant=var)
+    _, r2 = atm3.compute_forces(p, box, nu=NU)
+    torch.cuda.synchronize()
+    assert r["n_pairs"] == r2["n_pairs"]
+    assert r["e_lj"] == pytest.approx(r2["e_lj"], rel=1e-9)
+    assert r["w_lj"] == pytest.approx(r2["w_lj"], rel=1e-9)
+    sample = np.random.default_rng(11).choice(len(pos), 200, replace=False)
+    ref = orc.molecules(pos, box, rc=RC, nu=NU, truncation="product", variant=var, sample=sample)
+    fg = f.cpu().numpy().astype(np.float64)[sample]
+    assert force_err(fg, ref.forces) <= 1e-5
