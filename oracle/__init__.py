@@ -76,6 +76,8 @@ def _load():
         lib.orc_brute.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(ctypes.c_double),
                                   P(_Params), P(ctypes.c_double), P(_Result)]
         lib.orc_brute.restype = ctypes.c_int
+        lib.orc_brute_tensor.argtypes = lib.orc_brute.argtypes + [P(ctypes.c_double)]
+        lib.orc_brute_tensor.restype = ctypes.c_int
         lib.orc_molecules.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(ctypes.c_double),
                                       P(_Params), P(ctypes.c_int64), ctypes.c_int64,
                                       P(ctypes.c_double), P(_Result)]
@@ -151,6 +153,25 @@ def brute(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
     if lib.orc_brute(_dp(pos), len(pos), _dp(b), ctypes.byref(p), _dp(f), ctypes.byref(r)) != 0:
         raise ValueError("oracle: invalid arguments")
     return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+
+
+def virial_diag(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
+                variant="3c08", terms=3):
+    """Diagonal of the virial tensor, W_aa = sum over force pairs of r_a F_a,
+    for LJ and for ATM (the three force pairs of eq. (forcepairs) of every
+    included triplet), by the O(N^3) evaluation; returns (w_lj[3], w_atm[3],
+    Result)."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    b = np.ascontiguousarray(box, dtype=np.float64)
+    f = np.zeros_like(pos)
+    r = _Result()
+    w = np.zeros(6)
+    p = _params(rc, nu, eps, sigma, truncation, variant, terms)
+    if lib.orc_brute_tensor(_dp(pos), len(pos), _dp(b), ctypes.byref(p), _dp(f), ctypes.byref(r), _dp(w)) != 0:
+        raise ValueError("oracle: invalid arguments")
+    res = Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+    return w[:3].copy(), w[3:].copy(), res
 
 
 def molecules(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",

@@ -284,9 +284,13 @@ static inline int visited_3c01(const int32_t* cm, const int32_t* ca, const int32
  * number of molecule triplets the traversal visits regardless of distance
  * (3c01: receiving-molecule incidences), i.e. what eqs. (celltriplet),
  * (twoonetriplets) and (carttriplets) count over the visited cell sets.
+ * If wdiag is not NULL it receives the diagonal of the virial tensor,
+ * W_aa = sum over the force pairs of r_a F_a (the LJ pairs, and the three
+ * force pairs of eq. (forcepairs) of each included triplet, credited like
+ * the energy): wdiag[0..2] LJ xx, yy, zz, wdiag[3..5] ATM xx, yy, zz.
  * Returns 0, or -1 on invalid arguments. */
-int orc_brute(const double* pos, int64_t n, const double box[3], const orc_params* p,
-              double* forces, orc_result* res) {
+int orc_brute_tensor(const double* pos, int64_t n, const double box[3], const orc_params* p,
+                     double* forces, orc_result* res, double* wdiag) {
   int32_t nc[3];
   if (n < 1 || orc_grid(box, p->rc, nc) != 0) return -1;
   int32_t* cx = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)n);
@@ -302,6 +306,7 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
   memset(forces, 0, sizeof(double) * 3 * (size_t)n);
   double rc2 = p->rc * p->rc;
   double e2 = 0, w2 = 0, e3 = 0, w3 = 0;
+  double t2x = 0, t2y = 0, t2z = 0, t3x = 0, t3y = 0, t3z = 0;
   int64_t np = 0, nt = 0, ncand = 0;
 
   if (p->terms & 1) {
@@ -318,6 +323,9 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
         }
         e2 += u;
         w2 += f * x;
+        t2x += f * d[0] * d[0];
+        t2y += f * d[1] * d[1];
+        t2z += f * d[2] * d[2];
         ++np;
       }
   }
@@ -329,7 +337,7 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
 #endif
     double* fb = (double*)calloc((size_t)nth * 3 * (size_t)n, sizeof(double));
     if (!fb) { free(cx); free(r2); return -1; }
-#pragma omp parallel reduction(+ : e3, w3, nt, ncand)
+#pragma omp parallel reduction(+ : e3, w3, nt, ncand, t3x, t3y, t3z)
     {
       int tid = 0;
 #ifdef _OPENMP
@@ -369,6 +377,7 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
               if (recv[1]) F[3 * j + d] += -fij[d] + fjk[d];
               if (recv[2]) F[3 * k + d] += -fik[d] - fjk[d];
             }
+            const double share = (nr == 3) ? 1.0 : (double)nr / 3.0;
             if (nr == 3) {
               e3 += u;
               w3 += w;
@@ -376,6 +385,9 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
               e3 += u * (double)nr / 3.0;
               w3 += w * (double)nr / 3.0;
             }
+            t3x += share * (rij[0] * fij[0] + rik[0] * fik[0] + rjk[0] * fjk[0]);
+            t3y += share * (rij[1] * fij[1] + rik[1] * fik[1] + rjk[1] * fjk[1]);
+            t3z += share * (rij[2] * fij[2] + rik[2] * fik[2] + rjk[2] * fjk[2]);
             nt += (p->variant == 2) ? nr : 1;
           }
     }
@@ -390,9 +402,22 @@ int orc_brute(const double* pos, int64_t n, const double box[3], const orc_param
   res->n_pairs = np;
   res->n_triplets = nt;
   res->n_candidates = ncand;
+  if (wdiag) {
+    wdiag[0] = t2x;
+    wdiag[1] = t2y;
+    wdiag[2] = t2z;
+    wdiag[3] = t3x;
+    wdiag[4] = t3y;
+    wdiag[5] = t3z;
+  }
   free(cx);
   free(r2);
   return 0;
+}
+
+int orc_brute(const double* pos, int64_t n, const double box[3], const orc_params* p,
+              double* forces, orc_result* res) {
+  return orc_brute_tensor(pos, n, box, p, forces, res, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -466,3 +466,37 @@ def test_lrc_vanishes_for_uniform_density_and_flips_under_mirror():
     assert (fz1[near] > 0).mean() > 0.9
     # no net force: bins act on each other with opposite forces
     assert abs(fz1.sum()) < 1e-12 * np.abs(fz1).sum()
+
+
+# --------------------------------------------------------------------------
+# diagonal of the virial tensor (pressure tensor, the interface motivation)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("trunc,var", [("pair", "3c08"), ("product", "3c08"), ("product", "3c18"),
+                                       ("product", "3c01")])
+def test_virial_diagonal_trace_and_axis_permutation(orc, trunc, var):
+    """The trace equals the scalar virial (accumulated separately), and
+    permuting the axes of positions and box permutes the diagonal."""
+    box = np.array([11.0, 13.0, 14.0])
+    pos, _ = workloads.rsa(400, box, 0.85, seed=77)
+    wl, wa, r = orc.virial_diag(pos, box, truncation=trunc, variant=var)
+    assert wl.sum() == pytest.approx(r.w_lj, rel=1e-12)
+    assert wa.sum() == pytest.approx(r.w_atm, rel=1e-12)
+    assert wa.sum() == pytest.approx(9.0 * r.e_atm, rel=1e-9)
+    perm = [2, 0, 1]
+    wl2, wa2, _ = orc.virial_diag(pos[:, perm], box[perm], truncation=trunc, variant=var)
+    if var == "3c08" or trunc == "pair":  # cell sets are not symmetric under axis permutation otherwise
+        assert np.allclose(wl2, wl[perm], rtol=1e-12)
+        assert np.allclose(wa2, wa[perm], rtol=1e-10)
+
+
+def test_virial_diagonal_is_isotropic_on_a_perfect_crystal(orc):
+    """A perfect FCC lattice in a cubic box has cubic symmetry: equal
+    diagonal components (pair rule, where the triplet set does not depend on
+    the cell sets)."""
+    from paper_2510_21230_amd import workloads as w
+    pos = w.fcc_sites(4, 4, 4, (1.65, 1.65, 1.65)) + 0.3
+    box = np.array([6.6, 6.6, 6.6])
+    wl, wa, r = orc.virial_diag(pos, box, rc=2.2)
+    assert r.n_triplets > 0
+    assert np.allclose(wl, wl.mean(), rtol=1e-11)
+    assert np.allclose(wa, wa.mean(), rtol=1e-11)
