@@ -144,6 +144,20 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
 int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                         const atm3_params* params, float* forces, atm3_result* out);
 
+/* Diagonal of the virial tensor, W_aa = sum over force pairs of r_a F_a: the
+ * LJ pairs, and the three force pairs F_i(j)k, F_i(k)j, F_j(k)i of eq.
+ * (forcepairs) of every included triplet (the pressure tensor behind the
+ * surface tensions that motivate three-body forces at interfaces, Sec. 1).
+ * The trace is the scalar virial of atm3_compute_forces.
+ *   w_out  host, 6 FP64: LJ xx, yy, zz, then ATM xx, yy, zz (FP64 sums of
+ *          FP32 terms)
+ * Same arguments and preconditions as atm3_compute_forces; the pairwise
+ * cutoff uses the 3c08 sets (every cell set includes the same triplets),
+ * the product cutoff 3c08 or 3c18 (ATM3_EINVAL for 3c01).  Blocks until
+ * done.  ATM3_EOVERFLOW / ATM3_ERANGE as for the product rule. */
+int atm3_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
+                     const atm3_params* params, double w_out[6]);
+
 /* As atm3_compute_forces, but enqueue only: the result struct is written to
  * `out_dev` (device memory, sizeof(atm3_result) bytes) by the last kernel,
  * including its `status`.  Nothing blocks.  Argument checks happen on the

@@ -34,7 +34,7 @@ EXPORTS = (
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
     "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale", "atm3_md_slab_lrc",
-    "atm3_md_nvt_graph",
+    "atm3_md_nvt_graph", "atm3_virial_diag",
 )
 MLP_NPARAM = 43650
 MLP_NDESC = 64
@@ -145,6 +145,8 @@ def load():
         lib.atm3_md_nvt_graph.argtypes = [vp, vp, vp, i64, dptr, ctypes.POINTER(Params), i64, ctypes.c_double,
                                           ctypes.c_double, i64, i64, vp, vp, i64, ctypes.c_int32, vp]
         lib.atm3_md_nvt_graph.restype = ctypes.c_int
+        lib.atm3_virial_diag.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), dptr]
+        lib.atm3_virial_diag.restype = ctypes.c_int
         _lib = lib
         return lib
 
@@ -241,6 +243,18 @@ class Context:
                                                  ctypes.byref(p), ctypes.c_void_p(forces.data_ptr()),
                                                  ctypes.byref(r)))
         return forces, r.as_dict()
+
+    def virial_diag(self, pos, box, **kw):
+        """Diagonal of the virial tensor: (w_lj[3], w_atm[3]) as float64
+        arrays (xx, yy, zz); blocks."""
+        import numpy as np
+        pos = self._pos(pos)
+        p = make_params(**kw)
+        w = (ctypes.c_double * 6)()
+        self._stream()
+        self._check(self.lib.atm3_virial_diag(self.h, ctypes.c_void_p(pos.data_ptr()), pos.shape[0], _box(box),
+                                              ctypes.byref(p), w))
+        return np.array(w[:3]), np.array(w[3:])
 
     def compute_forces_async(self, pos, box, forces, result_dev, params: Params):
         """Enqueue one evaluation on the current stream; result_dev is a device

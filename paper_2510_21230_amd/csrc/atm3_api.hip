@@ -283,6 +283,30 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
   return ATM3_OK;
 }
 
+int atm3_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], const atm3_params* params,
+                     double w_out[6]) {
+  static_assert(sizeof(atm3_result) >= 7 * sizeof(double), "the result buffers hold the tensor and its status");
+  Grid g;
+  int r = prepare(ctx, pos, n, box, params, &g);
+  if (r) return r;
+  if (!w_out) return fail(ctx, ATM3_EINVAL, "w_out is NULL");
+  if (params->truncation == ATM3_TRUNC_PRODUCT && params->variant == ATM3_VARIANT_3C01)
+    return fail(ctx, ATM3_EINVAL, "the virial tensor is not available for 3c01 under the product rule");
+  hipError_t e = launch_binning(ctx, pos, n, g);
+  if (e == hipSuccess) e = launch_virial_diag(ctx, pos, n, g, *params, (double*)ctx->dres);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->hres, ctx->dres, 7 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "virial tensor");
+  double h[7];
+  memcpy(h, ctx->hres, sizeof(h));
+  const int status = (int)h[6];
+  if (status == ATM3_EOVERFLOW)
+    return fail(ctx, status, "the cells within reach of a cell hold more than 2048 molecules, or a cell set more than 512");
+  if (status == ATM3_ERANGE) return fail(ctx, status, "an ATM force term reached 2^18 (fixed-point accumulator range)");
+  for (int k = 0; k < 6; ++k) w_out[k] = h[k];
+  return ATM3_OK;
+}
+
 int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3], const atm3_params* params,
                         float* forces, atm3_result* out) {
   if (!out) return fail(ctx, ATM3_EINVAL, "result pointer is NULL");

@@ -142,5 +142,9 @@ hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params
                                  bool triple);
 hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
                            float* forces, atm3_result* res_dev);
+// Diagonal of the virial tensor into out_dev[0..5] (LJ xx, yy, zz; ATM xx,
+// yy, zz) and the status into out_dev[6]; needs the binning of `pos`.
+hipError_t launch_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
+                              double* out_dev);
 
 }  // namespace atm3

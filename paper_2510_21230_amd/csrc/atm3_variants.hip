@@ -146,6 +146,7 @@ struct OneArgs {
   float k3nu, k15nu, k075nu;
   float* forces;
   double* fout;               // if set, FP64 forces go here instead of `forces`
+  double* tpart;              // if set, per block LJ W_xx, W_yy, W_zz (half per molecule)
   double* dpart;              // per block: e_lj, w_lj, e_atm, unused
   unsigned long long* ipart;  // per block: n_pairs, n_triplets, unused, overflow
 };
@@ -257,6 +258,7 @@ struct OneLds {
   double facc[OS_WAVES][3];
   double red[OS_WAVES][3];
   unsigned long long redi[OS_WAVES][2];
+  double tred[OS_WAVES][3];
   int32_t nc;
 };
 
@@ -268,7 +270,7 @@ struct OneLds {
 // 64 at a time; pairs inside the band take the oracle's FP64 decision.  WV:
 // molecule-candidate vectors need a minimum-image wrap (fewer than 4 cells
 // per dimension); WJ: candidate-candidate vectors do (fewer than 8).
-template <bool WV, bool WJ>
+template <bool WV, bool WJ, bool TENSOR = false>
 __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   __shared__ OneLds L;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
   const int g = blockIdx.x % a.groups;
   const int cx = (int)(c % a.nx), cy = (int)((c / a.nx) % a.ny), cz = (int)(c / ((int64_t)a.nx * a.ny));
   constexpr int R = 1, span = 3, nnb = OS_NB, q0 = 13;
-  double e_lj = 0.0, w_lj = 0.0, e3 = 0.0;
+  double e_lj = 0.0, w_lj = 0.0, e3 = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
   unsigned long long npair = 0, ntrip = 0, over = 0;
   // neighbour cells (dx fastest) and their populations
   if (threadIdx.x < nnb) {
@@ -352,6 +354,11 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
             fz -= f * (double)v.z;
             e_lj += 0.5 * a.eps4 * (s12 - s6);
             w_lj += 0.5 * f * x;
+            if (TENSOR) {
+              tx += 0.5 * f * (double)(v.x * v.x);
+              ty += 0.5 * f * (double)(v.y * v.y);
+              tz += 0.5 * f * (double)(v.z * v.z);
+            }
             npair += (om < oj) ? 1 : 0;
           }
         }
@@ -460,14 +467,28 @@ __global__ __launch_bounds__(64 * OS_WAVES) void k_onesided(OneArgs a) {
     npair += __shfl_xor(npair, o);
     ntrip += __shfl_xor(ntrip, o);
   }
+  if (TENSOR)
+    for (int o = 32; o > 0; o >>= 1) {
+      tx += __shfl_xor(tx, o);
+      ty += __shfl_xor(ty, o);
+      tz += __shfl_xor(tz, o);
+    }
   if (lane == 0) {
     L.red[w][0] = e_lj;
     L.red[w][1] = w_lj;
     L.red[w][2] = e3;
     L.redi[w][0] = npair;
     L.redi[w][1] = ntrip;
+    L.tred[w][0] = tx;
+    L.tred[w][1] = ty;
+    L.tred[w][2] = tz;
   }
   __syncthreads();
+  if (TENSOR && threadIdx.x < 3) {
+    double t = 0.0;
+    for (int q = 0; q < OS_WAVES; ++q) t += L.tred[q][threadIdx.x];
+    a.tpart[3 * (int64_t)blockIdx.x + threadIdx.x] = t;
+  }
   if (threadIdx.x == 0) {
     for (int k = 0; k < 3; ++k) {
       double sum = 0.0;
@@ -519,6 +540,12 @@ struct ProdArgs {
   unsigned long long* acc;    // [3 n] fixed-point ATM forces, input order
   double* dpart;              // per block: 0, 0, 3 sum u, 0
   unsigned long long* ipart;  // per block: 0, n_triplets, range flag, overflow
+  // virial-tensor mode only: the pairwise cutoff instead of the product
+  // (rc^2 with the same relative band), and per-block W_xx, W_yy, W_zz
+  int32_t pair;
+  double rc2;
+  float lo2f, hi2f;
+  double* tpart;
 };
 
 struct ProdLds {
@@ -529,13 +556,14 @@ struct ProdLds {
   int32_t cnt[16], base[16], cell[16];
   double red[PB_WAVES];
   unsigned long long redi[PB_WAVES][2];
+  double tred[PB_WAVES][3];
 };
 
 // eq. (atm) and eq. (forcepairs) from the three pair vectors r_ij = r_i - r_j,
 // r_ik, r_jk and their squared lengths x, y, z: F_i = c_x r_ij + c_y r_ik,
 // F_j = -c_x r_ij + c_z r_jk (F_k = -F_i - F_j); returns u / nu.
 __device__ __forceinline__ float atm_vec(float3 ij, float3 ik, float3 jk, float x, float y, float z, float k3nu,
-                                         float k15nu, float k075nu, float3* fi, float3* fj) {
+                                         float k15nu, float k075nu, float3* fi, float3* fj, float3* c = nullptr) {
   const float s = x + y + z;
   const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
   const float AB = A * B, AC = A * C, BC = B * C;
@@ -556,6 +584,7 @@ __device__ __forceinline__ float atm_vec(float3 ij, float3 ik, float3 jk, float 
   fj->x = fmaf(cz, jk.x, -cx * ij.x);
   fj->y = fmaf(cz, jk.y, -cx * ij.y);
   fj->z = fmaf(cz, jk.z, -cx * ij.z);
+  if (c) *c = make_float3(cx, cy, cz);
   return fmaf(0.375f * P, t5, t3);
 }
 
@@ -563,7 +592,7 @@ __device__ __forceinline__ unsigned long long fix32(float v) {
   return (unsigned long long)(long long)rint((double)v * FIX_SCALE);
 }
 
-template <int VAR, bool WR>
+template <int VAR, bool WR, bool TENSOR = false>
 __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
   __shared__ ProdLds L;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -599,9 +628,10 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
   }
   __syncthreads();
   const int n = L.base[NCS];
-  double e3 = 0.0;
+  double e3 = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
   unsigned long long ntrip = 0, rng = 0;
   const unsigned long long over = n > PB_CAP ? 1 : 0;
+  const bool pair = TENSOR && a.pair;
   if (!over) {
     for (int q = w; q < NCS; q += PB_WAVES) {
       int dx, dy, dz;
@@ -634,15 +664,23 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
         const float3 ij = dvec(pi, pj), ik = dvec(pi, pk), jk = dvec(pj, pk);
         const float x = sq3(ij), y = sq3(ik), z = sq3(jk);
         bool in = true;
-        if (!((x * y) * z < a.lo6f) || fminf(x, fminf(y, z)) < a.small2) {
+        const bool near = pair ? !(fmaxf(x, fmaxf(y, z)) < a.lo2f) : !((x * y) * z < a.lo6f);
+        if (near || fminf(x, fminf(y, z)) < a.small2) {
           const int oi = __float_as_int(pi.w), oj = __float_as_int(pj.w), ok = __float_as_int(pk.w);
-          in = product_ok(exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]),
-                          exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]),
-                          exact_r2(a.pos, oj, ok, a.box[0], a.box[1], a.box[2]), a.rc6);
+          const double ex = exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]);
+          const double ey = exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]);
+          const double ez = exact_r2(a.pos, oj, ok, a.box[0], a.box[1], a.box[2]);
+          in = pair ? (ex < a.rc2 && ey < a.rc2 && ez < a.rc2) : product_ok(ex, ey, ez, a.rc6);
         }
         if (in) {
-          float3 fi, fj;
-          const float u = atm_vec(ij, ik, jk, x, y, z, a.k3nu, a.k15nu, a.k075nu, &fi, &fj);
+          float3 fi, fj, c;
+          const float u = atm_vec(ij, ik, jk, x, y, z, a.k3nu, a.k15nu, a.k075nu, &fi, &fj, &c);
+          if (TENSOR) {
+            // virial of the three force pairs: c_x r_ij r_ij + c_y r_ik r_ik + c_z r_jk r_jk
+            tx += (double)fmaf(c.x, ij.x * ij.x, fmaf(c.y, ik.x * ik.x, c.z * (jk.x * jk.x)));
+            ty += (double)fmaf(c.x, ij.y * ij.y, fmaf(c.y, ik.y * ik.y, c.z * (jk.y * jk.y)));
+            tz += (double)fmaf(c.x, ij.z * ij.z, fmaf(c.y, ik.z * ik.z, c.z * (jk.z * jk.z)));
+          }
           const float3 fk = make_float3(-(fi.x + fj.x), -(fi.y + fj.y), -(fi.z + fj.z));
           const float mx = fmaxf(fmaxf(fmaxf(fabsf(fi.x), fabsf(fi.y)), fmaxf(fabsf(fi.z), fabsf(fj.x))),
                                  fmaxf(fmaxf(fabsf(fj.y), fabsf(fj.z)),
@@ -684,7 +722,7 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
           if (k < n && (VAR != ATM3_VARIANT_3C08 || (L.code[k] & cij) == 0)) {
             const float4 pk = L.p[k];
             const float y = sq3(dvec(pi, pk)), z = sq3(dvec(pj, pk));
-            acc = (x * y) * z < a.hi6f || fminf(x, fminf(y, z)) < a.small2;
+            acc = (pair ? fmaxf(x, fmaxf(y, z)) < a.hi2f : (x * y) * z < a.hi6f) || fminf(x, fminf(y, z)) < a.small2;
           }
           const unsigned long long bits = __ballot(acc);
           if (acc)
@@ -715,13 +753,28 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
     e3 += __shfl_xor(e3, o);
     ntrip += __shfl_xor(ntrip, o);
     rng |= __shfl_xor(rng, o);
+    if (TENSOR) {
+      tx += __shfl_xor(tx, o);
+      ty += __shfl_xor(ty, o);
+      tz += __shfl_xor(tz, o);
+    }
   }
   if (lane == 0) {
     L.red[w] = e3;
     L.redi[w][0] = ntrip;
     L.redi[w][1] = rng;
+    if (TENSOR) {
+      L.tred[w][0] = tx;
+      L.tred[w][1] = ty;
+      L.tred[w][2] = tz;
+    }
   }
   __syncthreads();
+  if (TENSOR && threadIdx.x < 3) {
+    double t = 0.0;
+    for (int q = 0; q < PB_WAVES; ++q) t += L.tred[q][threadIdx.x];
+    a.tpart[3 * (int64_t)blockIdx.x + threadIdx.x] = t;
+  }
   if (threadIdx.x == 0) {
     double s = 0.0;
     unsigned long long t = 0, r = 0;
@@ -874,20 +927,149 @@ OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, con
   a.k075nu = (float)(0.75 * p.nu);
   a.forces = forces;
   a.fout = nullptr;
+  a.tpart = nullptr;
   *groups_out = groups;
   return a;
 }
 
+template <bool TENSOR = false>
 void launch_one(const OneArgs& a, unsigned nb, bool wv, bool wj, hipStream_t st) {
   if (wv)
-    hipLaunchKernelGGL((k_onesided<true, true>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+    hipLaunchKernelGGL((k_onesided<true, true, TENSOR>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
   else if (wj)
-    hipLaunchKernelGGL((k_onesided<false, true>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+    hipLaunchKernelGGL((k_onesided<false, true, TENSOR>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
   else
-    hipLaunchKernelGGL((k_onesided<false, false>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+    hipLaunchKernelGGL((k_onesided<false, false, TENSOR>), dim3(nb), dim3(64 * OS_WAVES), 0, st, a);
+}
+
+// Block-kernel arguments for base-cell grids of `splits` blocks per cell;
+// *wr: the grid needs minimum-image wraps inside a cell set (vectors span
+// under 2 cells for 3c08, 3 for 3c18).
+ProdArgs prod_args(const OneArgs& a, const Grid& g, int variant, int splits, unsigned long long* acc, bool* wr) {
+  ProdArgs b;
+  b.sorted = a.sorted;
+  b.start = a.start;
+  b.pos = a.pos;
+  b.nx = g.n[0];
+  b.ny = g.n[1];
+  b.nz = g.n[2];
+  b.splits = splits;
+  *wr = false;
+  for (int d = 0; d < 3; ++d) {
+    b.side[d] = a.side[d];
+    b.box[d] = a.box[d];
+    b.boxf[d] = a.boxf[d];
+    b.invf[d] = a.invf[d];
+    *wr = *wr || g.n[d] < (variant == ATM3_VARIANT_3C08 ? 4 : 6);
+  }
+  b.rc6 = a.rc6;
+  b.lo6f = a.lo6f;
+  b.hi6f = a.hi6f;
+  b.small2 = a.small2;
+  b.k3nu = a.k3nu;
+  b.k15nu = a.k15nu;
+  b.k075nu = a.k075nu;
+  b.acc = acc;
+  b.pair = 0;
+  b.rc2 = a.rc2;
+  b.lo2f = (float)(a.rc2 * (1.0 - 1e-4));
+  b.hi2f = (float)(a.rc2 * (1.0 + 1e-4));
+  b.tpart = nullptr;
+  return b;
+}
+
+template <bool TENSOR>
+void launch_prod(const ProdArgs& b, int variant, bool wr, unsigned nb, hipStream_t st) {
+  if (variant == ATM3_VARIANT_3C08) {
+    if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, true, TENSOR>), dim3(nb), dim3(64 * PB_WAVES), 0, st, b);
+    else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, false, TENSOR>), dim3(nb), dim3(64 * PB_WAVES), 0, st, b);
+  } else {
+    if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, true, TENSOR>), dim3(nb), dim3(64 * PB_WAVES), 0, st, b);
+    else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, false, TENSOR>), dim3(nb), dim3(64 * PB_WAVES), 0, st, b);
+  }
+}
+
+inline int prod_splits(const Grid& g) {
+  // small grids: several blocks per base cell so that about 2048 run
+  return (int)std::min<int64_t>(8, std::max<int64_t>(1, (2048 + g.ncells - 1) / g.ncells));
+}
+
+// Fixed-order sums of the virial-tensor partials: out[0..2] LJ, out[3..5]
+// ATM (blocks nb1..nb), out[6] the status as a number.
+__global__ __launch_bounds__(256) void k_tensor_final(const double* __restrict__ tpart,
+                                                      const unsigned long long* __restrict__ ipart, int32_t nb1,
+                                                      int32_t nb, double* __restrict__ out) {
+  __shared__ double sd[6][256];
+  __shared__ unsigned long long sf[2][256];
+  const int tid = threadIdx.x;
+  double d[6] = {0, 0, 0, 0, 0, 0};
+  unsigned long long over = 0, rng = 0;
+  for (int b = tid; b < nb; b += 256) {
+    for (int k = 0; k < 3; ++k) d[(b < nb1 ? 0 : 3) + k] += tpart[3 * (int64_t)b + k];
+    rng |= ipart[4 * (int64_t)b + 2];
+    over |= ipart[4 * (int64_t)b + 3];
+  }
+  for (int k = 0; k < 6; ++k) sd[k][tid] = d[k];
+  sf[0][tid] = over;
+  sf[1][tid] = rng;
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half) {
+      for (int k = 0; k < 6; ++k) sd[k][tid] += sd[k][tid + half];
+      sf[0][tid] |= sf[0][tid + half];
+      sf[1][tid] |= sf[1][tid + half];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int k = 0; k < 6; ++k) out[k] = sd[k][0];
+    out[6] = sf[0][0] ? (double)ATM3_EOVERFLOW : (sf[1][0] ? (double)ATM3_ERANGE : 0.0);
+  }
 }
 
 }  // namespace
+
+hipError_t launch_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
+                              double* out_dev) {
+  const bool lj = (p.terms & ATM3_TERM_LJ) != 0, atm = (p.terms & ATM3_TERM_ATM) != 0;
+  const bool pair = p.truncation == ATM3_TRUNC_PAIR;
+  // the pairwise cutoff includes the same triplets for every cell set
+  const int variant = pair ? ATM3_VARIANT_3C08 : p.variant;
+  int groups = 1;
+  bool wv = false, wj = false;
+  OneArgs a = one_args(ctx, pos, n, g, p, ATM3_TERM_LJ, nullptr, &groups, &wv, &wj);
+  const int splits = prod_splits(g);
+  const int64_t nb1_64 = lj ? g.ncells * groups : 0, nb2_64 = atm ? g.ncells * splits : 0;
+  if (nb1_64 + nb2_64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+  const unsigned nb1 = (unsigned)nb1_64, nb2 = (unsigned)nb2_64, nb = nb1 + nb2;
+  if (ensure(ctx, B_SRED, 88 * (size_t)nb + 64)) return hipErrorOutOfMemory;
+  double* dpart = (double*)ctx->s.p[B_SRED];
+  unsigned long long* ipart = (unsigned long long*)(dpart + 4 * (size_t)nb);
+  double* tpart = (double*)(ipart + 4 * (size_t)nb);
+  unsigned long long* acc = (unsigned long long*)ctx->s.p[B_FPART];
+  double* ljf = (double*)(acc + 3 * n);
+  hipStream_t st = ctx->stream;
+  if (nb1) {
+    a.dpart = dpart;
+    a.ipart = ipart;
+    a.fout = ljf;
+    a.tpart = tpart;
+    launch_one<true>(a, nb1, wv, wj, st);
+  }
+  if (nb2) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st, acc, 3 * n);
+    bool wr = false;
+    ProdArgs b = prod_args(a, g, variant, splits, acc, &wr);
+    b.pair = pair ? 1 : 0;
+    b.dpart = dpart + 4 * (size_t)nb1;
+    b.ipart = ipart + 4 * (size_t)nb1;
+    b.tpart = tpart + 3 * (size_t)nb1;
+    launch_prod<true>(b, variant, wr, nb2, st);
+  }
+  hipLaunchKernelGGL(k_tensor_final, dim3(1), dim3(256), 0, st, (const double*)tpart,
+                     (const unsigned long long*)ipart, (int32_t)nb1, (int32_t)nb, out_dev);
+  return hipGetLastError();
+}
 
 hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, const atm3_params& p,
                            float* forces, atm3_result* res_dev) {
@@ -901,8 +1083,7 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   bool wv = false, wj = false;
   OneArgs a = one_args(ctx, pos, n, g, p, one_terms, forces, &groups, &wv, &wj);
   const int64_t nb1_64 = one_terms ? g.ncells * groups : 0;
-  // small grids: several blocks per base cell so that about 2048 run
-  const int splits = (int)std::min<int64_t>(8, std::max<int64_t>(1, (2048 + g.ncells - 1) / g.ncells));
+  const int splits = prod_splits(g);
   const int64_t nb2_64 = (blockwise && atm) ? g.ncells * splits : 0;
   if (nb1_64 + nb2_64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
   const unsigned nb1 = (unsigned)nb1_64, nb2 = (unsigned)nb2_64, nb = nb1 + nb2;
@@ -928,40 +1109,11 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
     launch_one(a, nb1, wv, wj, st);
   }
   if (nb2) {
-    ProdArgs b;
-    b.sorted = a.sorted;
-    b.start = a.start;
-    b.pos = pos;
-    b.nx = g.n[0];
-    b.ny = g.n[1];
-    b.nz = g.n[2];
-    b.splits = splits;
     bool wr = false;
-    for (int d = 0; d < 3; ++d) {
-      b.side[d] = a.side[d];
-      b.box[d] = a.box[d];
-      b.boxf[d] = a.boxf[d];
-      b.invf[d] = a.invf[d];
-      // vectors inside a cell set span under 2 (3c08) or 3 (3c18) cells
-      wr = wr || g.n[d] < (p.variant == ATM3_VARIANT_3C08 ? 4 : 6);
-    }
-    b.rc6 = a.rc6;
-    b.lo6f = a.lo6f;
-    b.hi6f = a.hi6f;
-    b.small2 = a.small2;
-    b.k3nu = a.k3nu;
-    b.k15nu = a.k15nu;
-    b.k075nu = a.k075nu;
-    b.acc = acc;
+    ProdArgs b = prod_args(a, g, p.variant, splits, acc, &wr);
     b.dpart = dpart + 4 * (size_t)nb1;
     b.ipart = ipart + 4 * (size_t)nb1;
-    if (p.variant == ATM3_VARIANT_3C08) {
-      if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, true>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
-      else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C08, false>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
-    } else {
-      if (wr) hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, true>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
-      else hipLaunchKernelGGL((k_prod_block<ATM3_VARIANT_3C18, false>), dim3(nb2), dim3(64 * PB_WAVES), 0, st, b);
-    }
+    launch_prod<false>(b, p.variant, wr, nb2, st);
   }
   if (blockwise)
     hipLaunchKernelGGL(k_prod_forces, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st, lj ? (const double*)ljf : nullptr,

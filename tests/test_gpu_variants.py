@@ -133,3 +133,31 @@ def test_product_rule_fcc32k_sampled(torch_cuda, orc, var):
     ref = orc.molecules(pos, box, rc=RC, nu=NU, truncation="product", variant=var, sample=sample)
     fg = f.cpu().numpy().astype(np.float64)[sample]
     assert force_err(fg, ref.forces) <= 1e-5
+
+
+@pytest.mark.parametrize("trunc,var,terms", [("pair", "3c08", 3), ("pair", "3c18", 2), ("product", "3c08", 3),
+                                             ("product", "3c18", 3), ("product", "3c08", 1)])
+def test_virial_diagonal_against_oracle(torch_cuda, orc, trunc, var, terms):
+    """atm3_virial_diag: the diagonal of the LJ and ATM virial tensors
+    against the O(N^3) oracle (1e-5 of the largest component), and the
+    trace equal to the scalar virial of atm3_compute_forces."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    box = np.array([13.0, 14.0, 15.5])
+    pos, _ = workloads.rsa(900, box, dmin=0.85, seed=workloads.SEED_BASE + 720)
+    _say(f"[virial tensor {trunc} {var} terms={terms}] n={len(pos)}")
+    wl_ref, wa_ref, ref = orc.virial_diag(pos, box, rc=RC, nu=NU, truncation=trunc, variant=var, terms=terms)
+    ctx = atm3.context(0)
+    p = torch.from_numpy(pos).cuda()
+    wl, wa = ctx.virial_diag(p, box, rc=RC, nu=NU, truncation=trunc, variant=var, terms=terms)
+    _, r = atm3.compute_forces(p, box, rc=RC, nu=NU, truncation=trunc, variant=var, terms=terms)
+    _say(f"  lj {wl} (ref {wl_ref})  atm {wa} (ref {wa_ref})")
+    for got, want in ((wl, wl_ref), (wa, wa_ref)):
+        scale = max(np.abs(want).max(), 1e-12)
+        assert np.abs(got - want).max() <= 1e-5 * scale
+    if terms & 1:
+        assert wl.sum() == pytest.approx(r["w_lj"], rel=1e-6)
+    if terms & 2:
+        assert wa.sum() == pytest.approx(r["w_atm"], rel=1e-5)
+    else:
+        assert np.all(wa == 0.0)
