@@ -51,7 +51,7 @@ class _Result(ctypes.Structure):
     _fields_ = [("e_lj", ctypes.c_double), ("e_atm", ctypes.c_double),
                 ("w_lj", ctypes.c_double), ("w_atm", ctypes.c_double),
                 ("n_pairs", ctypes.c_int64), ("n_triplets", ctypes.c_int64),
-                ("n_candidates", ctypes.c_int64)]
+                ("n_candidates", ctypes.c_int64), ("n_distinct", ctypes.c_int64)]
 
 
 _lib = None
@@ -87,6 +87,11 @@ def _load():
         lib.orc_triplet.restype = None
         lib.orc_visited.argtypes = [P(ctypes.c_int32)] * 4 + [ctypes.c_int]
         lib.orc_visited.restype = ctypes.c_int
+        lib.orc_cells.argtypes = [P(ctypes.c_double), ctypes.c_int64, P(ctypes.c_double), P(_Params),
+                                  ctypes.c_int64, ctypes.c_int64, P(ctypes.c_double), P(_Result)]
+        lib.orc_cells.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = None
         lib.orc_threads.argtypes = []
         lib.orc_threads.restype = ctypes.c_int
         _lib = lib
@@ -112,6 +117,7 @@ class Result:
     n_pairs: int
     n_triplets: int
     n_candidates: int
+    n_distinct: int = -1  # included triplets counted once (brute force only)
 
 
 def _params(rc, nu, eps, sigma, truncation, variant, terms):
@@ -152,7 +158,7 @@ def brute(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
     p = _params(rc, nu, eps, sigma, truncation, variant, terms)
     if lib.orc_brute(_dp(pos), len(pos), _dp(b), ctypes.byref(p), _dp(f), ctypes.byref(r)) != 0:
         raise ValueError("oracle: invalid arguments")
-    return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+    return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates, r.n_distinct)
 
 
 def virial_diag(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
@@ -170,7 +176,7 @@ def virial_diag(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair
     p = _params(rc, nu, eps, sigma, truncation, variant, terms)
     if lib.orc_brute_tensor(_dp(pos), len(pos), _dp(b), ctypes.byref(p), _dp(f), ctypes.byref(r), _dp(w)) != 0:
         raise ValueError("oracle: invalid arguments")
-    res = Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+    res = Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates, r.n_distinct)
     return w[:3].copy(), w[3:].copy(), res
 
 
@@ -195,7 +201,28 @@ def molecules(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, truncation="pair",
                                 _dp(f), ctypes.byref(r))
     if rc_ != 0:
         raise ValueError("oracle: invalid arguments")
-    return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates)
+    return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates, r.n_distinct)
+
+
+def cells(pos, box, rc=2.5, nu=0.073, eps=1.0, sigma=1.0, terms=3, base_cells=None) -> Result:
+    """Linked-cell evaluation with Newton 3 over the 3c08 cell sets, pairwise
+    cutoff (the CPU counterpart of the method's structure, for timing).
+    ``base_cells=(b0, b1)`` restricts it to that range of base cells."""
+    lib = _load()
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    b = np.ascontiguousarray(box, dtype=np.float64)
+    f = np.zeros_like(pos)
+    r = _Result()
+    p = _params(rc, nu, eps, sigma, "pair", "3c08", terms)
+    b0, b1 = base_cells if base_cells is not None else (0, 0)
+    if lib.orc_cells(_dp(pos), len(pos), _dp(b), ctypes.byref(p), int(b0), int(b1), _dp(f), ctypes.byref(r)) != 0:
+        raise ValueError("oracle: invalid arguments (pairwise cutoff, >= 3 cells per dimension)")
+    return Result(f, r.e_lj, r.e_atm, r.w_lj, r.w_atm, r.n_pairs, r.n_triplets, r.n_candidates, r.n_distinct)
+
+
+def set_threads(k: int) -> None:
+    """Number of OpenMP threads for the oracle's parallel loops."""
+    _load().orc_set_threads(int(k))
 
 
 def threads() -> int:

@@ -50,6 +50,7 @@ typedef struct {
 typedef struct {
   double e_lj, e_atm, w_lj, w_atm;
   int64_t n_pairs, n_triplets, n_candidates;
+  int64_t n_distinct; /* distinct included triplets (3c01: at least one receiver) */
 } orc_result;
 
 /* ------------------------------------------------------------------------ */
@@ -283,7 +284,9 @@ static inline int visited_3c01(const int32_t* cm, const int32_t* ca, const int32
  * r.F, eq. (P_3) for the three-body part) and counts.  n_candidates is the
  * number of molecule triplets the traversal visits regardless of distance
  * (3c01: receiving-molecule incidences), i.e. what eqs. (celltriplet),
- * (twoonetriplets) and (carttriplets) count over the visited cell sets.
+ * (twoonetriplets) and (carttriplets) count over the visited cell sets;
+ * n_distinct counts every included triplet once (for 3c01, n_triplets counts
+ * receiving molecules, up to three per triplet).
  * If wdiag is not NULL it receives the diagonal of the virial tensor,
  * W_aa = sum over the force pairs of r_a F_a (the LJ pairs, and the three
  * force pairs of eq. (forcepairs) of each included triplet, credited like
@@ -307,7 +310,7 @@ int orc_brute_tensor(const double* pos, int64_t n, const double box[3], const or
   double rc2 = p->rc * p->rc;
   double e2 = 0, w2 = 0, e3 = 0, w3 = 0;
   double t2x = 0, t2y = 0, t2z = 0, t3x = 0, t3y = 0, t3z = 0;
-  int64_t np = 0, nt = 0, ncand = 0;
+  int64_t np = 0, nt = 0, ndist = 0, ncand = 0;
 
   if (p->terms & 1) {
     for (int64_t i = 0; i < n; ++i)
@@ -337,7 +340,7 @@ int orc_brute_tensor(const double* pos, int64_t n, const double box[3], const or
 #endif
     double* fb = (double*)calloc((size_t)nth * 3 * (size_t)n, sizeof(double));
     if (!fb) { free(cx); free(r2); return -1; }
-#pragma omp parallel reduction(+ : e3, w3, nt, ncand, t3x, t3y, t3z)
+#pragma omp parallel reduction(+ : e3, w3, nt, ndist, ncand, t3x, t3y, t3z)
     {
       int tid = 0;
 #ifdef _OPENMP
@@ -389,6 +392,7 @@ int orc_brute_tensor(const double* pos, int64_t n, const double box[3], const or
             t3y += share * (rij[1] * fij[1] + rik[1] * fik[1] + rjk[1] * fjk[1]);
             t3z += share * (rij[2] * fij[2] + rik[2] * fik[2] + rjk[2] * fjk[2]);
             nt += (p->variant == 2) ? nr : 1;
+            ++ndist;
           }
     }
     for (int t = 0; t < nth; ++t)
@@ -402,6 +406,7 @@ int orc_brute_tensor(const double* pos, int64_t n, const double box[3], const or
   res->n_pairs = np;
   res->n_triplets = nt;
   res->n_candidates = ncand;
+  res->n_distinct = ndist;
   if (wdiag) {
     wdiag[0] = t2x;
     wdiag[1] = t2y;
@@ -586,11 +591,191 @@ int orc_molecules(const double* pos, int64_t n, const double box[3], const orc_p
   res->n_pairs = np;
   res->n_triplets = nt;
   res->n_candidates = -1;
+  res->n_distinct = -1;
   free(cx);
   free(cl);
   free(start);
   free(order);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Linked-cell evaluation with Newton's third law over the 3c08 cell sets   */
+/* (Sec. 4): the CPU reference of the method's own structure, used to time  */
+/* the oracle against the GPU.  Every base cell b takes the 2x2x2 block of  */
+/* cells b + o, o in {0,1}^3 (corner code o = ox + 2 oy + 4 oz); a pair or  */
+/* triplet of molecules of the block belongs to b iff b is the             */
+/* componentwise minimum of its cells, i.e. the AND of the corner codes is */
+/* 0, so every pair and triplet of the 3c08 sets is evaluated exactly once */
+/* (eqs. celltriplet, twoonetriplets, carttriplets count them).  Pairwise   */
+/* cutoff only: under it these sets hold every included triplet.  The       */
+/* arithmetic per pair and per triplet is that of orc_brute (minimum image, */
+/* eq. ATMGradient term by term, eq. forcepairs, eq. P_3); only the order   */
+/* of the force sums differs.  Base cells [b0, b1) only when b1 > b0 (a     */
+/* bounded sample for timing: the forces then hold that sample's share).   */
+/* Returns 0, or -1 on invalid arguments, the product cutoff, or fewer than */
+/* 3 cells per dimension.                                                   */
+/* ------------------------------------------------------------------------ */
+static int64_t comb2_(int64_t m) { return m * (m - 1) / 2; }
+static int64_t comb3_(int64_t m) { return m * (m - 1) * (m - 2) / 6; }
+
+int orc_cells(const double* pos, int64_t n, const double box[3], const orc_params* p,
+              int64_t b0, int64_t b1, double* forces, orc_result* res) {
+  int32_t nc[3];
+  if (n < 1 || p->truncation != 0 || orc_grid(box, p->rc, nc) != 0) return -1;
+  for (int d = 0; d < 3; ++d)
+    if (nc[d] < 3) return -1;
+  const int64_t ncells = (int64_t)nc[0] * nc[1] * nc[2];
+  if (b1 <= b0) { b0 = 0; b1 = ncells; }
+  if (b0 < 0 || b1 > ncells) return -1;
+  int32_t* cl = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int64_t* start = (int64_t*)calloc((size_t)ncells + 1, sizeof(int64_t));
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  if (!cl || !start || !order) { free(cl); free(start); free(order); return -1; }
+  orc_bin(pos, n, box, nc, NULL, cl);
+  for (int64_t i = 0; i < n; ++i) start[cl[i] + 1]++;
+  for (int64_t c = 0; c < ncells; ++c) start[c + 1] += start[c];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncells);
+    memcpy(fill, start, sizeof(int64_t) * (size_t)ncells);
+    for (int64_t i = 0; i < n; ++i) order[fill[cl[i]]++] = i;
+    free(fill);
+  }
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  double* fb = (double*)calloc((size_t)nth * 3 * (size_t)n, sizeof(double));
+  if (!fb) { free(cl); free(start); free(order); return -1; }
+  const double rc2 = p->rc * p->rc;
+  double e2 = 0, w2 = 0, e3 = 0, w3 = 0;
+  int64_t np = 0, nt = 0, ncand = 0;
+  int fail = 0;
+
+#pragma omp parallel reduction(+ : e2, w2, e3, w3, np, nt, ncand) reduction(| : fail)
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    double* F = fb + (size_t)tid * 3 * (size_t)n;
+    int64_t cap = 0;
+    int64_t* loc = NULL;  /* molecules of the block */
+    int* code = NULL;     /* their corner codes     */
+    double* dv = NULL;    /* minimum-image r_a - r_b of every ordered pair */
+    double* r2 = NULL;    /* its squared length                            */
+#pragma omp for schedule(dynamic, 8)
+    for (int64_t b = b0; b < b1; ++b) {
+      const int bx = (int)(b % nc[0]), by = (int)((b / nc[0]) % nc[1]), bz = (int)(b / ((int64_t)nc[0] * nc[1]));
+      int64_t pop[8], m = 0;
+      for (int o = 0; o < 8; ++o) {
+        int cx = (bx + (o & 1)) % nc[0], cy = (by + ((o >> 1) & 1)) % nc[1], cz = (bz + (o >> 2)) % nc[2];
+        int64_t c = ((int64_t)cz * nc[1] + cy) * nc[0] + cx;
+        pop[o] = start[c + 1] - start[c];
+        m += pop[o];
+      }
+      /* molecule triplets of the visited cell sets, eqs. (celltriplet),
+       * (twoonetriplets), (carttriplets) */
+      ncand += comb3_(pop[0]);
+      for (int o = 0; o < 8; ++o)
+        for (int q = o + 1; q < 8; ++q) {
+          if ((o & q) == 0) ncand += pop[q] * comb2_(pop[o]) + pop[o] * comb2_(pop[q]);
+          for (int r = q + 1; r < 8; ++r)
+            if ((o & q & r) == 0) ncand += pop[o] * pop[q] * pop[r];
+        }
+      if (m > cap) {
+        cap = 2 * m;
+        free(loc); free(code); free(dv); free(r2);
+        loc = (int64_t*)malloc(sizeof(int64_t) * (size_t)cap);
+        code = (int*)malloc(sizeof(int) * (size_t)cap);
+        dv = (double*)malloc(sizeof(double) * 3 * (size_t)cap * (size_t)cap);
+        r2 = (double*)malloc(sizeof(double) * (size_t)cap * (size_t)cap);
+        if (!loc || !code || !dv || !r2) { fail = 1; cap = 0; continue; }
+      }
+      m = 0;
+      for (int o = 0; o < 8; ++o) {
+        int cx = (bx + (o & 1)) % nc[0], cy = (by + ((o >> 1) & 1)) % nc[1], cz = (bz + (o >> 2)) % nc[2];
+        int64_t c = ((int64_t)cz * nc[1] + cy) * nc[0] + cx;
+        for (int64_t s = start[c]; s < start[c + 1]; ++s) {
+          loc[m] = order[s];
+          code[m] = o;
+          ++m;
+        }
+      }
+      for (int64_t a = 0; a < m; ++a)
+        for (int64_t q = a + 1; q < m; ++q) {
+          double* d = dv + 3 * (a * m + q);
+          min_image(pos + 3 * loc[a], pos + 3 * loc[q], box, d);
+          r2[a * m + q] = sqlen(d);
+        }
+      if (p->terms & 1) {
+        for (int64_t a = 0; a < m; ++a)
+          for (int64_t q = a + 1; q < m; ++q) {
+            const double x = r2[a * m + q];
+            if ((code[a] & code[q]) != 0 || !(x < rc2)) continue;
+            const double* d = dv + 3 * (a * m + q);
+            double u, f;
+            lj_pair(x, p->eps, p->sigma, &u, &f);
+            for (int k = 0; k < 3; ++k) {
+              F[3 * loc[a] + k] += f * d[k];
+              F[3 * loc[q] + k] -= f * d[k];
+            }
+            e2 += u;
+            w2 += f * x;
+            ++np;
+          }
+      }
+      if (p->terms & 2) {
+        for (int64_t a = 0; a < m; ++a)
+          for (int64_t q = a + 1; q < m; ++q) {
+            const double x = r2[a * m + q];
+            if (!(x < rc2)) continue;
+            for (int64_t k = q + 1; k < m; ++k) {
+              if ((code[a] & code[q] & code[k]) != 0) continue;
+              const double y = r2[a * m + k], z = r2[q * m + k];
+              if (!truncation_ok(x, y, z, p->rc, 0)) continue;
+              double fij[3], fik[3], fjk[3], u, w;
+              atm_force_pairs(dv + 3 * (a * m + q), dv + 3 * (a * m + k), dv + 3 * (q * m + k), x, y, z, p->nu,
+                              fij, fik, fjk, &u, &w);
+              for (int d = 0; d < 3; ++d) {
+                F[3 * loc[a] + d] += fij[d] + fik[d];
+                F[3 * loc[q] + d] += -fij[d] + fjk[d];
+                F[3 * loc[k] + d] += -fik[d] - fjk[d];
+              }
+              e3 += u;
+              w3 += w;
+              ++nt;
+            }
+          }
+      }
+    }
+    free(loc); free(code); free(dv); free(r2);
+  }
+  memset(forces, 0, sizeof(double) * 3 * (size_t)n);
+  for (int t = 0; t < nth; ++t)
+    for (int64_t q = 0; q < 3 * n; ++q) forces[q] += fb[(size_t)t * 3 * (size_t)n + q];
+  free(fb);
+  free(cl);
+  free(start);
+  free(order);
+  res->e_lj = e2;
+  res->w_lj = w2;
+  res->e_atm = e3;
+  res->w_atm = w3;
+  res->n_pairs = np;
+  res->n_triplets = nt;
+  res->n_candidates = ncand;
+  res->n_distinct = nt;
+  return fail ? -1 : 0;
+}
+
+/* Sets the number of OpenMP threads of the oracle's parallel loops. */
+void orc_set_threads(int k) {
+#ifdef _OPENMP
+  if (k > 0) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
 }
 
 /* Number of OpenMP threads the oracle's parallel loops use. */
