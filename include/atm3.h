@@ -335,20 +335,27 @@ int atm3_md_slab_lrc(atm3_ctx* ctx, const double* pos, int64_t n, const double b
  * lrc_bins > 0 (histogram added to `profile` if not NULL); atm3_md_kick;
  * atm3_md_rescale to `temperature` with `dof` degrees of freedom.  The
  * result struct of step k (k = 1..steps) is written to
- * rows + (k / sample_every - 1) * row_stride when sample_every divides k.
+ * rows + (k / sample_every - 1) * row_stride when sample_every divides k,
+ * and the status of every evaluation (the initial one and every step,
+ * sampled or not) is folded into the status
+ * field of the row after the last sample, rows + nsamp * row_stride with
+ * nsamp = steps / sample_every, as the minimum of the statuses (so any
+ * failure, being negative, stays there); the caller sets that field to
+ * ATM3_OK before the call.
  * Before the first step the forces at the initial positions are computed
  * (with the correction).  The trajectory and the rows are bit-identical to
  * the same calls made one by one.
  *   pos, vel  device, n*3 FP64, updated in place
  *   forces    device, n*3 FP32 scratch, holds the last step's forces
- *   rows      device, (steps / sample_every) * row_stride bytes, caller-owned
+ *   rows      device, (steps / sample_every + 1) * row_stride bytes,
+ *             caller-owned
  *   profile   device, lrc_bins int64, or NULL
  * Ordered after the work already enqueued on the context stream; returns
  * when the run has finished.  Errors: ATM3_EINVAL for the conditions of the
  * calls it makes, steps or sample_every < 1, row_stride not a multiple of 8
  * or below sizeof(atm3_result), ATM3_FLAG_CHECK_FINITE set, or profiling
- * enabled (neither can be captured); a failed evaluation is reported in its
- * row's status. */
+ * enabled (neither can be captured); a failed evaluation is reported in the
+ * folded status of row nsamp, and in its own row if it was sampled. */
 int atm3_md_nvt_graph(atm3_ctx* ctx, double* pos, double* vel, int64_t n, const double box[3],
                       const atm3_params* params, int64_t steps, double dt, double temperature, int64_t dof,
                       int64_t sample_every, float* forces, void* rows, int64_t row_stride, int32_t lrc_bins,

@@ -532,43 +532,57 @@ def md_nvt(pos, vel, box, steps, dt, temperature, sample_every=1, lrc_bins=0, pr
     f = torch.empty((n, 3), dtype=torch.float32, device=pos.device)
     stride = 128  # bytes per result row (>= sizeof(atm3_result), aligned)
     ns = steps // sample_every
-    rows = torch.zeros((ns + 1) * stride, dtype=torch.uint8, device=pos.device)
     lrc = dict(rc=prm.rc, eps=prm.eps, sigma=prm.sigma)
     if profile is not None and not (profile.is_cuda and profile.dtype == torch.int64 and profile.is_contiguous()
                                     and profile.numel() == lrc_bins):
         raise ValueError("profile must be a contiguous int64 device tensor of lrc_bins entries")
     if graph:
+        # rows 0..ns-1: sampled steps; row ns: status folded over every step
+        rows = torch.zeros((ns + 1) * stride, dtype=torch.uint8, device=pos.device)
         ctx._stream()
         ctx._check(lib.atm3_md_nvt_graph(ctx.h, _ptr(pos), _ptr(vel), n, _box(box), ctypes.byref(prm), int(steps),
                                          float(dt), float(temperature), 3 * n - 3, int(sample_every), _ptr(f),
                                          _ptr(rows), stride, int(lrc_bins),
                                          None if profile is None else _ptr(profile)))
-        return _rows_out(rows, ns, stride)
-    ctx.compute_forces_async(pos, box, f, rows[ns * stride:], prm)  # spare row
+        return _rows_out(rows, stride, [q for q in range(ns)], [ns])
+    # one row per step (row k-1 for step k) and row `steps` for the initial
+    # forces, so that every evaluation's status is checked, sampled or not
+    rows = torch.zeros((steps + 1) * stride, dtype=torch.uint8, device=pos.device)
+    ctx.compute_forces_async(pos, box, f, rows[steps * stride:], prm)
     if lrc_bins:
         ctx.slab_lrc(pos, box, f, lrc_bins, **lrc)
     for k in range(1, steps + 1):
         ctx._check(lib.atm3_md_kick_drift(ctx.h, _ptr(pos), _ptr(vel), _ptr(f), n, float(dt)))
-        row = (k // sample_every - 1) if k % sample_every == 0 else ns
-        ctx.compute_forces_async(pos, box, f, rows[row * stride:], prm)
+        ctx.compute_forces_async(pos, box, f, rows[(k - 1) * stride:], prm)
         if lrc_bins:
             ctx.slab_lrc(pos, box, f, lrc_bins, hist_sum=profile, **lrc)
         ctx._check(lib.atm3_md_kick(ctx.h, _ptr(vel), _ptr(f), n, float(dt)))
         ctx._check(lib.atm3_md_rescale(ctx.h, _ptr(vel), n, float(temperature), 3 * n - 3))
-    return _rows_out(rows, ns, stride)
+    return _rows_out(rows, stride, [sample_every * (q + 1) - 1 for q in range(ns)], range(steps + 1))
 
 
-def _rows_out(rows, ns, stride):
-    """(ns, 4) e_lj, e_atm, w_lj, w_atm of the result rows; raises on a failed
-    evaluation."""
-    import numpy as np
+def _rows_out(rows, stride, sampled, checked):
+    """(len(sampled), 4) e_lj, e_atm, w_lj, w_atm of the result rows with the
+    indices `sampled`; raises if any row of `checked` holds a failed status."""
     import torch
     torch.cuda.synchronize(rows.device)
-    host = rows.cpu().numpy()
-    out = np.zeros((ns, 4))
-    for q in range(ns):
-        r = Result.from_buffer_copy(host[q * stride:q * stride + ctypes.sizeof(Result)].tobytes())
-        if r.status != 0:
-            raise Atm3Error(int(r.status), f"force evaluation of sample {q} returned status {int(r.status)}")
-        out[q] = (r.e_lj, r.e_atm, r.w_lj, r.w_atm)
+    return rows_from_bytes(rows.cpu().numpy().tobytes(), stride, sampled, checked)
+
+
+def rows_from_bytes(host: bytes, stride, sampled, checked):
+    """Host part of _rows_out: decode result rows from raw bytes."""
+    import numpy as np
+    size = ctypes.sizeof(Result)
+
+    def row(q):
+        return Result.from_buffer_copy(host[q * stride:q * stride + size])
+
+    for q in checked:
+        st = int(row(q).status)
+        if st != 0:
+            raise Atm3Error(st, f"force evaluation of row {q} returned status {st}")
+    out = np.zeros((len(sampled), 4))
+    for a, q in enumerate(sampled):
+        r = row(q)
+        out[a] = (r.e_lj, r.e_atm, r.w_lj, r.w_atm)
     return out

@@ -128,15 +128,25 @@ __global__ __launch_bounds__(256) void k_lrc_apply(LrcArgs a) {
 
 // Step counter of a graph-launched run: the result of every sample_every-th
 // step goes to its row (the graph's kernels take fixed arguments, so the row
-// is chosen on the device).
+// is chosen on the device), and every step's status is folded into the
+// status of row nsamp (the minimum: the most negative failure code wins).
 __global__ void k_md_store(const uint64_t* __restrict__ slot, uint8_t* __restrict__ rows, int64_t stride,
                            int64_t* __restrict__ ctr, int64_t sample_every, int64_t nsamp) {
   __shared__ int64_t c;
-  if (threadIdx.x == 0) c = ++ctr[0];
+  if (threadIdx.x == 0) {
+    c = ++ctr[0];
+    const int32_t st = ((const atm3_result*)slot)->status;
+    atomicMin(&((atm3_result*)(rows + nsamp * stride))->status, st);
+  }
   __syncthreads();
   if (c % sample_every != 0 || c / sample_every > nsamp) return;
   uint64_t* dst = (uint64_t*)(rows + (c / sample_every - 1) * stride);
   for (int k = threadIdx.x; k < (int)(sizeof(atm3_result) / 8); k += blockDim.x) dst[k] = slot[k];
+}
+
+// Folds one evaluation's status into the run-wide status word.
+__global__ void k_md_fold(const atm3_result* __restrict__ slot, int32_t* __restrict__ status) {
+  if (threadIdx.x == 0) atomicMin(status, slot->status);
 }
 
 __global__ void k_zero_i64(int64_t* p) {
@@ -288,6 +298,8 @@ int atm3_md_nvt_graph(atm3_ctx* ctx, double* pos, double* vel, int64_t n, const 
   const int np = (int)((3 * n + KE_CHUNK - 1) / KE_CHUNK);
   if ((r = ensure(ctx, B_SRED, 8 * (size_t)np + 64))) return r;
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, ctx->stream, ctr);
+  hipLaunchKernelGGL(k_md_fold, dim3(1), dim3(64), 0, ctx->stream, slot,
+                     &((atm3_result*)((uint8_t*)rows + (steps / sample_every) * row_stride))->status);
 
   hipStream_t user = ctx->stream, s = nullptr;
   hipEvent_t e0 = nullptr;
