@@ -165,6 +165,27 @@ int atm3_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const double b
 int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                               const atm3_params* params, float* forces, atm3_result* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * atm3_compute_forces_async with the pairwise cutoff (any cell set), but
+ * every scratch buffer of the evaluation is carved from one fixed device
+ * array of ATM3_NOALLOC_BYTES that the library holds on each device it runs
+ * on until the process ends.  The call allocates nothing; the caller still
+ * provides pos, forces and out_dev.  Outputs are bit-identical to
+ * atm3_compute_forces_async with the same arguments.
+ * Limits: n <= ATM3_NOALLOC_MAX_N and at most ATM3_NOALLOC_MAX_CELLS cells
+ * (ATM3_EINVAL beyond them, before anything is enqueued); the product
+ * cutoff and enabled phase timing return ATM3_EINVAL.
+ * Every call on a device shares that device's array and leaves its last
+ * contents there: calls that overlap on one device (two contexts, two
+ * streams, or two threads) race and give undefined results; calls ordered
+ * on one stream are safe.  Other errors as atm3_compute_forces_async. */
+#define ATM3_NOALLOC_MAX_N 65536
+#define ATM3_NOALLOC_MAX_CELLS 65536
+#define ATM3_NOALLOC_BYTES (20 << 20)
+int atm3_compute_forces_noalloc(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
+                                const atm3_params* params, float* forces, atm3_result* out_dev);
+
 /* Kernel timing with HIP events recorded on the context stream around each
  * phase of atm3_compute_forces[_async]:
  *   ATM3_PHASE_BINNING  wrap/cell index, counting sort, coordinate gather

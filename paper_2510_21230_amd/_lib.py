@@ -34,8 +34,10 @@ EXPORTS = (
     "atm3_mlp_set_stats", "atm3_mlp_get_stats", "atm3_mlp_fit_stats", "atm3_surrogate_forces",
     "atm3_mlp_grad", "atm3_mlp_adam", "atm3_mlp_train_step", "atm3_surrogate_pairs",
     "atm3_md_kick_drift", "atm3_md_kick", "atm3_md_kinetic", "atm3_md_rescale", "atm3_md_slab_lrc",
-    "atm3_md_nvt_graph", "atm3_virial_diag",
+    "atm3_md_nvt_graph", "atm3_virial_diag", "atm3_compute_forces_noalloc",
 )
+NOALLOC_MAX_N = 65536
+NOALLOC_MAX_CELLS = 65536
 MLP_NPARAM = 43650
 MLP_NDESC = 64
 PHASES = {"binning": 0, "block": 1, "big": 2, "reduce": 3}
@@ -98,6 +100,8 @@ def load():
         lib.atm3_compute_forces.restype = ctypes.c_int
         lib.atm3_compute_forces_async.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), vp, vp]
         lib.atm3_compute_forces_async.restype = ctypes.c_int
+        lib.atm3_compute_forces_noalloc.argtypes = [vp, vp, i64, dptr, ctypes.POINTER(Params), vp, vp]
+        lib.atm3_compute_forces_noalloc.restype = ctypes.c_int
         lib.atm3_profile_enable.argtypes = [vp, ctypes.c_int]
         lib.atm3_profile_enable.restype = ctypes.c_int
         lib.atm3_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -265,6 +269,15 @@ class Context:
             self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box), ctypes.byref(params),
             ctypes.c_void_p(forces.data_ptr()), ctypes.c_void_p(result_dev.data_ptr())))
 
+    def compute_forces_noalloc(self, pos, box, forces, result_dev, params: Params):
+        """As compute_forces_async, with every scratch buffer in the library's
+        fixed device array (no device allocation; pairwise cutoff, at most
+        NOALLOC_MAX_N molecules and NOALLOC_MAX_CELLS cells)."""
+        n = pos.shape[0]
+        self._stream()
+        self._check(self.lib.atm3_compute_forces_noalloc(
+            self.h, ctypes.c_void_p(pos.data_ptr()), n, _box(box), ctypes.byref(params),
+            ctypes.c_void_p(forces.data_ptr()), ctypes.c_void_p(result_dev.data_ptr())))
 
     def slab_lrc(self, pos, box, forces, nbins=600, rc=2.5, eps=1.0, sigma=1.0, hist_sum=None):
         """Add the planar long-range correction of the LJ force to the z

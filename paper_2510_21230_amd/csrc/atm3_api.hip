@@ -2,6 +2,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -21,6 +22,10 @@ int hip_fail(atm3_ctx* ctx, hipError_t e, const char* what) {
 
 int ensure(atm3_ctx* ctx, Buf b, size_t bytes) {
   if (bytes == 0) bytes = 256;
+  if (ctx->fixed) {  // carve of the fixed array: never allocate
+    if (ctx->bufcap[b] >= bytes) return ATM3_OK;
+    return fail(ctx, ATM3_EINVAL, "evaluation exceeds the fixed scratch array of the no-allocation entry point");
+  }
   if (ctx->s.cap[b] >= bytes) return ATM3_OK;
   if (ctx->s.p[b]) {
     hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -37,6 +42,24 @@ int ensure(atm3_ctx* ctx, Buf b, size_t bytes) {
   }
   ctx->s.cap[b] = want;
   return ATM3_OK;
+}
+
+void plan_pair_path(int64_t n, const Grid& g, size_t bytes[B_NBUF]) {
+  for (int b = 0; b < B_NBUF; ++b) bytes[b] = 0;
+  const size_t N = (size_t)n, C = (size_t)g.ncells;
+  bytes[B_CELL_OF] = 4 * N;
+  bytes[B_RANK] = 4 * N;
+  bytes[B_COUNT] = 4 * C;
+  bytes[B_START] = 4 * (C + 1);
+  bytes[B_PERM] = 4 * N;
+  bytes[B_SORTED] = 32 * N;
+  bytes[B_FPART] = 8 * 24 * N;
+  bytes[B_BLKD] = 8 * 3 * C;
+  bytes[B_BLKI] = 4 * 2 * C;
+  bytes[B_DEFER] = 4 * (2 * C + 3);
+  bytes[B_RED] = reduce_scratch_bytes();
+  bytes[B_TILE] = 4 * (C / 1024 + 2);
+  bytes[B_SRED] = 8 * ((C + 255) / 256) + 64;  // candidate counts of 3c18 / 3c01
 }
 
 static hipError_t phase_event(atm3_ctx* ctx, int phase, int which) {
@@ -93,7 +116,8 @@ int check_box(atm3_ctx* ctx, const double* box, double rc) {
   return ATM3_OK;
 }
 
-int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, const atm3_params* p, Grid* g) {
+// Argument checks and the cell grid, without touching device memory.
+int validate(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, const atm3_params* p, Grid* g) {
   if (!ctx) return ATM3_EINVAL;
   ctx->err.clear();
   if (!p) return fail(ctx, ATM3_EINVAL, "params is NULL");
@@ -120,31 +144,55 @@ int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, cons
       return fail(ctx, ATM3_EINVAL,
                   "box too small: floor(L/rc) = " + std::to_string(g->n[d]) + " < " + std::to_string(need) +
                       " cells in some dimension");
-  int r = set_device(ctx);
+  return set_device(ctx);
+}
+
+// The finite check of ATM3_FLAG_CHECK_FINITE (blocks until it has run).
+int check_finite(atm3_ctx* ctx, const double* pos, int64_t n) {
+  int32_t* bad = (int32_t*)ctx->buf[B_DEFER];
+  hipError_t e = launch_check_finite(ctx->stream, pos, n, bad);
+  if (e == hipSuccess) e = hipMemcpyAsync(ctx->hres, bad, 4, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "finite check");
+  int32_t flag = 0;
+  memcpy(&flag, ctx->hres, 4);
+  if (flag) return fail(ctx, ATM3_ERANGE, "a position is not finite");
+  return ATM3_OK;
+}
+
+int prepare(atm3_ctx* ctx, const double* pos, int64_t n, const double* box, const atm3_params* p, Grid* g) {
+  int r = validate(ctx, pos, n, box, p, g);
   if (r) return r;
-  const size_t N = (size_t)n, C = (size_t)g->ncells;
-  if ((r = ensure(ctx, B_CELL_OF, 4 * N))) return r;
-  if ((r = ensure(ctx, B_RANK, 4 * N))) return r;
-  if ((r = ensure(ctx, B_COUNT, 4 * C))) return r;
-  if ((r = ensure(ctx, B_START, 4 * (C + 1)))) return r;
-  if ((r = ensure(ctx, B_PERM, 4 * N))) return r;
-  if ((r = ensure(ctx, B_SORTED, 32 * N))) return r;
-  if ((r = ensure(ctx, B_FPART, 8 * 24 * N))) return r;
-  if ((r = ensure(ctx, B_BLKD, 8 * 3 * C))) return r;
-  if ((r = ensure(ctx, B_BLKI, 4 * 2 * C))) return r;
-  if ((r = ensure(ctx, B_DEFER, 4 * (2 * C + 3)))) return r;
-  if ((r = ensure(ctx, B_RED, reduce_scratch_bytes()))) return r;
-  if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
-  if (p->flags & ATM3_FLAG_CHECK_FINITE) {
-    int32_t* bad = (int32_t*)ctx->s.p[B_DEFER];
-    hipError_t e = launch_check_finite(ctx->stream, pos, n, bad);
-    if (e == hipSuccess) e = hipMemcpyAsync(ctx->hres, bad, 4, hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "finite check");
-    int32_t flag = 0;
-    memcpy(&flag, ctx->hres, 4);
-    if (flag) return fail(ctx, ATM3_ERANGE, "a position is not finite");
-  }
+  size_t bytes[B_NBUF];
+  plan_pair_path(n, *g, bytes);
+  for (int b = 0; b < B_NBUF; ++b)
+    if (bytes[b] && b != B_SRED && (r = ensure(ctx, (Buf)b, bytes[b]))) return r;
+  if (p->flags & ATM3_FLAG_CHECK_FINITE) return check_finite(ctx, pos, n);
+  return ATM3_OK;
+}
+
+// The fixed device array of the no-allocation entry point, one copy per
+// device, and its device address on each device (hipGetSymbolAddress once
+// per device, with that device current, at context creation).  Host code
+// uses only these addresses, never the array's name.
+constexpr int NOALLOC_MAXDEV = 64;
+std::mutex noalloc_mu;
+void* noalloc_addr[NOALLOC_MAXDEV] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[ATM3_NOALLOC_BYTES];
+
+namespace {
+
+int noalloc_init(atm3_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= NOALLOC_MAXDEV) return ATM3_EDEVICE;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_addr[ctx->device]) return ATM3_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) return ATM3_EDEVICE;
+  noalloc_addr[ctx->device] = ptr;
   return ATM3_OK;
 }
 
@@ -175,6 +223,12 @@ int atm3_create(atm3_ctx** out, int device_ordinal) {
     (void)hipFree(ctx->dres);
     delete ctx;
     return ATM3_ENOMEM;
+  }
+  if (noalloc_init(ctx) != ATM3_OK) {
+    (void)hipHostFree(ctx->hres);
+    (void)hipFree(ctx->dres);
+    delete ctx;
+    return ATM3_EDEVICE;
   }
   *out = ctx;
   return ATM3_OK;
@@ -256,10 +310,10 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
   if ((r = ensure(ctx, B_TILE, 4 * (C / 1024 + 2)))) return r;
   hipError_t e = launch_binning(ctx, pos, n, g);
   if (e != hipSuccess) return hip_fail(ctx, e, "binning launch");
-  e = hipMemcpyAsync(cell_of, ctx->s.p[B_CELL_OF], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
+  e = hipMemcpyAsync(cell_of, ctx->buf[B_CELL_OF], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(cell_start, ctx->s.p[B_START], 4 * (C + 1), hipMemcpyDeviceToDevice, ctx->stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(perm, ctx->s.p[B_PERM], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
+    e = hipMemcpyAsync(cell_start, ctx->buf[B_START], 4 * (C + 1), hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(perm, ctx->buf[B_PERM], 4 * N, hipMemcpyDeviceToDevice, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
   return ATM3_OK;
 }
@@ -279,6 +333,53 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
     if (e == hipSuccess && params->variant != ATM3_VARIANT_3C08)
       e = launch_variant_counts(ctx, g, *params, out_dev, true);
   }
+  if (e != hipSuccess) return hip_fail(ctx, e, "force launch");
+  return ATM3_OK;
+}
+
+int atm3_compute_forces_noalloc(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
+                                const atm3_params* params, float* forces, atm3_result* out_dev) {
+  Grid g;
+  int r = validate(ctx, pos, n, box, params, &g);
+  if (r) return r;
+  if (!forces || !out_dev) return fail(ctx, ATM3_EINVAL, "forces / result pointer is NULL");
+  if (params->truncation != ATM3_TRUNC_PAIR)
+    return fail(ctx, ATM3_EINVAL, "the no-allocation entry point evaluates the pairwise cutoff only");
+  if (ctx->profile) return fail(ctx, ATM3_EINVAL, "phase timing is not available without allocation");
+  if (n > ATM3_NOALLOC_MAX_N || g.ncells > ATM3_NOALLOC_MAX_CELLS)
+    return fail(ctx, ATM3_EINVAL,
+                "no-allocation limits exceeded: n = " + std::to_string(n) + " (max " +
+                    std::to_string(ATM3_NOALLOC_MAX_N) + "), cells = " + std::to_string(g.ncells) + " (max " +
+                    std::to_string(ATM3_NOALLOC_MAX_CELLS) + ")");
+  unsigned char* base = (unsigned char*)noalloc_addr[ctx->device];
+  if (!base) return fail(ctx, ATM3_EDEVICE, "the fixed scratch array has no address on this device");
+  size_t bytes[B_NBUF];
+  plan_pair_path(n, g, bytes);
+  void* table[B_NBUF] = {};
+  size_t cap[B_NBUF] = {};
+  size_t off = 0;
+  for (int b = 0; b < B_NBUF; ++b) {
+    if (!bytes[b]) continue;
+    off = (off + 255) & ~(size_t)255;
+    table[b] = base + off;
+    cap[b] = bytes[b];
+    off += bytes[b];
+  }
+  if (off > (size_t)ATM3_NOALLOC_BYTES)
+    return fail(ctx, ATM3_EINVAL, "evaluation exceeds the fixed scratch array of the no-allocation entry point");
+  ctx->buf = table;
+  ctx->bufcap = cap;
+  ctx->fixed = true;
+  hipError_t e = hipSuccess;
+  if (params->flags & ATM3_FLAG_CHECK_FINITE) r = check_finite(ctx, pos, n);
+  if (!r) e = launch_binning(ctx, pos, n, g);
+  if (!r && e == hipSuccess) e = launch_forces(ctx, pos, n, g, *params, forces, out_dev);
+  if (!r && e == hipSuccess && params->variant != ATM3_VARIANT_3C08)
+    e = launch_variant_counts(ctx, g, *params, out_dev, true);
+  ctx->buf = ctx->s.p;
+  ctx->bufcap = ctx->s.cap;
+  ctx->fixed = false;
+  if (r) return r;
   if (e != hipSuccess) return hip_fail(ctx, e, "force launch");
   return ATM3_OK;
 }

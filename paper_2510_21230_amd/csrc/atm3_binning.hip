@@ -187,12 +187,12 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
     g.side[d] = gr.side[d];
   }
   hipStream_t st = ctx->stream;
-  int32_t* cell_of = (int32_t*)ctx->s.p[B_CELL_OF];
-  int32_t* rank = (int32_t*)ctx->s.p[B_RANK];
-  int32_t* count = (int32_t*)ctx->s.p[B_COUNT];
-  int32_t* start = (int32_t*)ctx->s.p[B_START];
-  int32_t* perm = (int32_t*)ctx->s.p[B_PERM];
-  double4* sorted = (double4*)ctx->s.p[B_SORTED];
+  int32_t* cell_of = (int32_t*)ctx->buf[B_CELL_OF];
+  int32_t* rank = (int32_t*)ctx->buf[B_RANK];
+  int32_t* count = (int32_t*)ctx->buf[B_COUNT];
+  int32_t* start = (int32_t*)ctx->buf[B_START];
+  int32_t* perm = (int32_t*)ctx->buf[B_PERM];
+  double4* sorted = (double4*)ctx->buf[B_SORTED];
   const int32_t nn = (int32_t)n;
   unsigned fb = blocks_for(gr.ncells, 256);
   if (fb > 4096) fb = 4096;
@@ -201,7 +201,7 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
   hipLaunchKernelGGL(k_fill_i32, dim3(fb), dim3(256), 0, st, count, gr.ncells, 0);
   hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, nn, g, cell_of, rank, count);
   const int32_t ntiles = (int32_t)((gr.ncells + TILE - 1) / TILE);
-  int32_t* tile_sum = (int32_t*)ctx->s.p[B_TILE];
+  int32_t* tile_sum = (int32_t*)ctx->buf[B_TILE];
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, st, count, start, tile_sum, gr.ncells);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
   hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, tile_sum, gr.ncells,

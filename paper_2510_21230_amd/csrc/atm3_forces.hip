@@ -1214,13 +1214,13 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
                          float* forces, atm3_result* res_dev) {
   hipStream_t st = ctx->stream;
   ForceArgs a;
-  a.sorted = (const double4*)ctx->s.p[B_SORTED];
-  a.start = (const int32_t*)ctx->s.p[B_START];
+  a.sorted = (const double4*)ctx->buf[B_SORTED];
+  a.start = (const int32_t*)ctx->buf[B_START];
   a.pos = pos;
-  a.fpart = (u64*)ctx->s.p[B_FPART];
-  a.blkd = (double*)ctx->s.p[B_BLKD];
-  a.blki = (int32_t*)ctx->s.p[B_BLKI];
-  a.defer = (int32_t*)ctx->s.p[B_DEFER];
+  a.fpart = (u64*)ctx->buf[B_FPART];
+  a.blkd = (double*)ctx->buf[B_BLKD];
+  a.blki = (int32_t*)ctx->buf[B_BLKI];
+  a.defer = (int32_t*)ctx->buf[B_DEFER];
   a.ntot = (int32_t)n;
   a.nx = g.n[0];
   a.ny = g.n[1];
@@ -1255,8 +1255,8 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   if ((e = phase_end(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_REDUCE)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n, 256)), dim3(256), 0, st, (const u64*)a.fpart,
-                     (const int32_t*)ctx->s.p[B_PERM], (int32_t)n, forces);
-  RedPart* part = (RedPart*)ctx->s.p[B_RED];
+                     (const int32_t*)ctx->buf[B_PERM], (int32_t)n, forces);
+  RedPart* part = (RedPart*)ctx->buf[B_RED];
   Red1Args r1;
   r1.blkd = a.blkd;
   r1.blki = a.blki;

@@ -98,7 +98,10 @@ struct atm3_ctx {
   atm3::PhaseTimer timer[atm3::NPHASE];
   hipStream_t stream = nullptr;
   std::string err;
-  atm3::Scratch s;
+  atm3::Scratch s;               // owned device scratch (grow-only)
+  void** buf = s.p;              // buffer table the launches use: s.p, or a
+  size_t* bufcap = s.cap;        // carve of the fixed array (no allocation)
+  bool fixed = false;            // inside atm3_compute_forces_noalloc
   atm3_result* dres = nullptr;  // device result of the synchronous path
   atm3_result* hres = nullptr;  // pinned host copy
 };
@@ -113,6 +116,11 @@ hipError_t phase_end(atm3_ctx* ctx, int phase);
 int fail(atm3_ctx* ctx, int code, const std::string& msg);
 int hip_fail(atm3_ctx* ctx, hipError_t e, const char* what);
 int ensure(atm3_ctx* ctx, Buf b, size_t bytes);
+
+// Device scratch sizes of one pairwise-cutoff evaluation of n molecules on
+// grid g (every buffer the binning, block, reduction and candidate-count
+// launches use); zero for the buffers they do not touch.
+void plan_pair_path(int64_t n, const Grid& g, size_t bytes[B_NBUF]);
 
 // Grid from box and cutoff; returns false if any n_d < 1 or sizes overflow.
 bool make_grid(const double box[3], double rc, Grid* g);

@@ -201,7 +201,7 @@ int atm3_md_kinetic(atm3_ctx* ctx, const double* vel, int64_t n, double* ke_out)
   const int64_t m = 3 * n;
   const int np = (int)((m + KE_CHUNK - 1) / KE_CHUNK);
   if ((r = ensure(ctx, B_SRED, 8 * (size_t)np + 64))) return r;
-  double* part = (double*)ctx->s.p[B_SRED];
+  double* part = (double*)ctx->buf[B_SRED];
   hipLaunchKernelGGL(k_ke_part, dim3(np), dim3(256), 0, ctx->stream, vel, m, part + 1);
   hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(64), 0, ctx->stream, part + 1, np, part);
   hipError_t e = hipGetLastError();
@@ -220,7 +220,7 @@ int atm3_md_rescale(atm3_ctx* ctx, double* vel, int64_t n, double temperature, i
   const int64_t m = 3 * n;
   const int np = (int)((m + KE_CHUNK - 1) / KE_CHUNK);
   if ((r = ensure(ctx, B_SRED, 8 * (size_t)np + 64))) return r;
-  double* part = (double*)ctx->s.p[B_SRED];
+  double* part = (double*)ctx->buf[B_SRED];
   hipLaunchKernelGGL(k_ke_part, dim3(np), dim3(256), 0, ctx->stream, vel, m, part + 1);
   hipLaunchKernelGGL(k_ke_final, dim3(1), dim3(64), 0, ctx->stream, part + 1, np, part);
   hipLaunchKernelGGL(k_rescale, dim3(blocks_for(m, 256)), dim3(256), 0, ctx->stream, vel, m, (const double*)part,
@@ -242,8 +242,8 @@ int atm3_md_slab_lrc(atm3_ctx* ctx, const double* pos, int64_t n, const double b
   if (!(eps > 0.0) || !(sigma > 0.0)) return fail(ctx, ATM3_EINVAL, "eps and sigma must be > 0");
   // histogram (uint32) and bin forces (FP64) in one scratch buffer
   if ((r = ensure(ctx, B_ZHIST, 12 * (size_t)nbins + 16))) return r;
-  uint32_t* hist = (uint32_t*)ctx->s.p[B_ZHIST];
-  double* fbin = (double*)((char*)ctx->s.p[B_ZHIST] + ((4 * (size_t)nbins + 15) & ~(size_t)15));
+  uint32_t* hist = (uint32_t*)ctx->buf[B_ZHIST];
+  double* fbin = (double*)((char*)ctx->buf[B_ZHIST] + ((4 * (size_t)nbins + 15) & ~(size_t)15));
   const double inv = (double)nbins / box[2];
   hipLaunchKernelGGL(k_zero_u32, dim3(blocks_for(nbins, 256)), dim3(256), 0, ctx->stream, hist, nbins);
   hipLaunchKernelGGL(k_zhist, dim3(blocks_for(n, 256)), dim3(256), 0, ctx->stream, pos, n, box[2], inv, nbins,
@@ -286,8 +286,8 @@ int atm3_md_nvt_graph(atm3_ctx* ctx, double* pos, double* vel, int64_t n, const 
   if (!(temperature > 0.0) || !isfinite(temperature)) return fail(ctx, ATM3_EINVAL, "temperature must be > 0");
   if (dof < 1 || dof > 3 * n) return fail(ctx, ATM3_EINVAL, "dof must be in [1, 3n]");
   if ((r = ensure(ctx, B_MDSLOT, sizeof(atm3_result) + 64))) return r;
-  atm3_result* slot = (atm3_result*)ctx->s.p[B_MDSLOT];
-  int64_t* ctr = (int64_t*)((char*)ctx->s.p[B_MDSLOT] + ((sizeof(atm3_result) + 15) & ~(size_t)15));
+  atm3_result* slot = (atm3_result*)ctx->buf[B_MDSLOT];
+  int64_t* ctr = (int64_t*)((char*)ctx->buf[B_MDSLOT] + ((sizeof(atm3_result) + 15) & ~(size_t)15));
   // every scratch buffer a step uses is sized before the capture (no
   // allocation or synchronisation may happen inside it): the initial forces,
   // and the kinetic-energy partials of the thermostat

@@ -1138,7 +1138,7 @@ struct SurGeom {
 
 template <class T>
 T* buf(atm3_ctx* ctx, Buf b) {
-  return (T*)ctx->s.p[b];
+  return (T*)ctx->buf[b];
 }
 
 // Binning, neighbour lists and descriptors (FP32 and BF16).

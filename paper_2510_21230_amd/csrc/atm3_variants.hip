@@ -863,13 +863,13 @@ hipError_t launch_variant_counts(atm3_ctx* ctx, const Grid& g, const atm3_params
   const unsigned nb = blocks_for(g.ncells, 256);
   if (ensure(ctx, B_SRED, 8 * (size_t)nb + 64)) return hipErrorOutOfMemory;
   CandArgs a;
-  a.start = (const int32_t*)ctx->s.p[B_START];
+  a.start = (const int32_t*)ctx->buf[B_START];
   a.nx = g.n[0];
   a.ny = g.n[1];
   a.nz = g.n[2];
   a.ncells = g.ncells;
   a.variant = p.variant;
-  a.part = (unsigned long long*)ctx->s.p[B_SRED];
+  a.part = (unsigned long long*)ctx->buf[B_SRED];
   hipLaunchKernelGGL(k_cand, dim3(nb), dim3(256), 0, ctx->stream, a);
   hipLaunchKernelGGL(k_cand_final, dim3(1), dim3(64), 0, ctx->stream, a.part, (int32_t)nb, p.variant,
                      triple ? 1 : 0, res_dev);
@@ -889,8 +889,8 @@ OneArgs one_args(atm3_ctx* ctx, const double* pos, int64_t n, const Grid& g, con
   int64_t groups64 = std::min<int64_t>(64, std::max<int64_t>(1, (per_cell + OS_MOLS - 1) / OS_MOLS));
   if (!(terms & ATM3_TERM_ATM)) groups64 = std::min<int64_t>(groups64, (2048 + g.ncells - 1) / g.ncells);
   const int groups = (int)groups64;
-  a.sorted = (const double4*)ctx->s.p[B_SORTED];
-  a.start = (const int32_t*)ctx->s.p[B_START];
+  a.sorted = (const double4*)ctx->buf[B_SORTED];
+  a.start = (const int32_t*)ctx->buf[B_START];
   a.pos = pos;
   a.nx = g.n[0];
   a.ny = g.n[1];
@@ -1043,10 +1043,10 @@ hipError_t launch_virial_diag(atm3_ctx* ctx, const double* pos, int64_t n, const
   if (nb1_64 + nb2_64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
   const unsigned nb1 = (unsigned)nb1_64, nb2 = (unsigned)nb2_64, nb = nb1 + nb2;
   if (ensure(ctx, B_SRED, 88 * (size_t)nb + 64)) return hipErrorOutOfMemory;
-  double* dpart = (double*)ctx->s.p[B_SRED];
+  double* dpart = (double*)ctx->buf[B_SRED];
   unsigned long long* ipart = (unsigned long long*)(dpart + 4 * (size_t)nb);
   double* tpart = (double*)(ipart + 4 * (size_t)nb);
-  unsigned long long* acc = (unsigned long long*)ctx->s.p[B_FPART];
+  unsigned long long* acc = (unsigned long long*)ctx->buf[B_FPART];
   double* ljf = (double*)(acc + 3 * n);
   hipStream_t st = ctx->stream;
   if (nb1) {
@@ -1091,11 +1091,11 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   // of launch_variant_counts (so that its ensure does not reallocate)
   const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
   if (ensure(ctx, B_SRED, need > need_c ? need : need_c)) return hipErrorOutOfMemory;
-  double* dpart = (double*)ctx->s.p[B_SRED];
+  double* dpart = (double*)ctx->buf[B_SRED];
   unsigned long long* ipart = (unsigned long long*)(dpart + 4 * (size_t)nb);
   // B_FPART (24 doubles per molecule) holds the fixed-point ATM forces and
   // the FP64 LJ forces of the block path
-  unsigned long long* acc = (unsigned long long*)ctx->s.p[B_FPART];
+  unsigned long long* acc = (unsigned long long*)ctx->buf[B_FPART];
   double* ljf = (double*)(acc + 3 * n);
   hipStream_t st = ctx->stream;
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
