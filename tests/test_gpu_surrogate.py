@@ -123,6 +123,24 @@ def test_pairs_descriptors_and_forward(torch_cuda):
     assert eerr <= 1e-2
     # Newton 3 holds exactly up to FP32 summation
     assert np.linalg.norm(F.sum(axis=0)) <= 1e-4 * frms * np.sqrt(len(pos))
+    # against the FP64 model itself (no operand rounding): rounding to
+    # bfloat16 perturbs each operand by at most 2^-9 relative, and eight
+    # rounded operand sets lie on the path to s and t (inputs, W1, H1, W2, H2,
+    # W3, H3, W4), so to first order the outputs move by at most 8 * 2^-9 of
+    # their dot products' absolute sums: the mean deviation is bounded by
+    # that, relative to the RMS output, and the largest by 4 times that
+    # (cancellation inside a dot product)
+    bound = 8 * 2.0 ** -9
+    f64 = S.forward(params, D, pairs, disp, RC, bf16_ops=False)
+    for key, got in (("s", st[:, 0]), ("t", st[:, 1])):
+        rr = np.sqrt(np.mean(f64[key] ** 2))
+        d = np.abs(got - f64[key]) / rr
+        _say(f"  {key} against FP64: max {d.max():.2e} mean {d.mean():.2e} (bounds {4 * bound:.2e} / {bound:.2e})")
+        assert d.mean() <= bound and d.max() <= 4 * bound
+    frms64 = np.sqrt(np.mean(np.sum(f64["F"] ** 2, axis=1)))
+    dF = np.linalg.norm(F - f64["F"], axis=1) / frms64
+    _say(f"  F against FP64: max {dF.max():.2e} rms {np.sqrt(np.mean(dF ** 2)):.2e}")
+    assert np.sqrt(np.mean(dF ** 2)) <= bound and dF.max() <= 4 * bound
 
 
 def test_fit_stats(torch_cuda):
