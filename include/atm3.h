@@ -182,7 +182,7 @@ int atm3_compute_forces_async(atm3_ctx* ctx, const double* pos, int64_t n, const
  * on one stream are safe.  Other errors as atm3_compute_forces_async. */
 #define ATM3_NOALLOC_MAX_N 65536
 #define ATM3_NOALLOC_MAX_CELLS 65536
-#define ATM3_NOALLOC_BYTES (20 << 20)
+#define ATM3_NOALLOC_BYTES (24 << 20)
 int atm3_compute_forces_noalloc(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
                                 const atm3_params* params, float* forces, atm3_result* out_dev);
 

@@ -28,6 +28,9 @@ SOURCES = {
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # atomics of a wave to one address: a DPP wave reduction and one atomic,
+    # not a loop over the active lanes
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=DPP",
     "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]

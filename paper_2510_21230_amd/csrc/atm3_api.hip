@@ -59,6 +59,8 @@ void plan_pair_path(int64_t n, const Grid& g, size_t bytes[B_NBUF]) {
   bytes[B_DEFER] = 4 * (2 * C + 3);
   bytes[B_RED] = reduce_scratch_bytes();
   bytes[B_TILE] = 4 * (C / 1024 + 2);
+  bytes[B_FMASK] = 4 * 14 * N;
+  bytes[B_FMOK] = 4 * C;
   bytes[B_SRED] = 8 * ((C + 255) / 256) + 64;  // candidate counts of 3c18 / 3c01
 }
 

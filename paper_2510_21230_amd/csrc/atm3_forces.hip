@@ -64,6 +64,8 @@ struct ForceArgs {
   double* blkd;           // [C][3]: e_lj', w_lj', e_atm'
   int32_t* blki;          // [C][2]: pairs, triplets
   int32_t* defer;         // [0] count, [1] status, [2..] base cells
+  const uint32_t* fmask;  // [N][14] forward-shell pair masks (k_fmask)
+  const int32_t* fm_ok;   // [C] 1 if a cell's mask words were written
   int32_t ntot;
   int32_t nx, ny, nz;
   int32_t ncells;
@@ -185,6 +187,7 @@ __device__ int64_t candidates_3c08(const int32_t* N) {
 struct BlockHead {
   int32_t cbase[9];
   int32_t cstart[8];
+  int32_t okc[8];  // the corner cells' mask words exist (fm_ok)
   int32_t bad;
   double red[3][NWAVE];
   long long redi[NWAVE];
@@ -203,6 +206,7 @@ __device__ int block_cells(const ForceArgs& a, int b, BlockHead& H) {
     const int s0 = a.start[c];
     H.cstart[tid] = s0;
     H.cbase[tid + 1] = a.start[c + 1] - s0;
+    H.okc[tid] = a.fm_ok ? a.fm_ok[c] : 0;
   }
   __syncthreads();
   if (tid == 0) {
@@ -345,11 +349,149 @@ __device__ void block_flush(const ForceArgs& a, int b, int n, const uint8_t* sco
 }
 
 // ---------------------------------------------------------------------------
-// Fast path: at most 128 molecules.  The upper-triangle pair masks are built
-// one wave per row; one thread per mask word then lists the upper pairs
-// (PCAP at most) and the upper pairs the block owns (PCAP/2 at most) in
-// row-major order.  The pairs with a non-empty K (about a third of them) are
-// sorted by |K| with their K words, at most KCAP of them.
+// Forward-shell pair masks, computed once per evaluation for every pair of
+// neighbouring molecules (the 2x2x2 blocks would otherwise test a pair of one
+// cell in 8 blocks, of face-neighbour cells in 4, of edge neighbours in 2).
+// For the molecule in sorted slot s of cell A and the k-th forward cell B_k
+// of A (FWD order: A itself, then the 13 neighbours at offsets whose
+// (dz, dy, dx) is lexicographically positive), word fmask[14 s + k] has bit t
+// set iff molecule t of B_k (t after s within A itself) lies inside rc by the
+// exact decision.  Cells of more than 32 molecules get no words; fm_ok[c]
+// says whether cell c's words were written.  One workgroup per row segment of
+// FM_G cells along x stages the forward region of the segment in LDS (the
+// segment's row and four neighbouring rows, one cell wider on each side).
+// ---------------------------------------------------------------------------
+constexpr int FM_G = 8;
+constexpr int FM_W = FM_G + 2;          // staged cells per row
+constexpr int FM_ROWS = 5;              // (dy, dz) = (0,0), (1,0), (-1,1), (0,1), (1,1)
+constexpr int FM_CELLS = FM_ROWS * FM_W;
+constexpr int FM_CAP = 1280;            // staged molecules
+
+// Index in FWD of the forward offset (dx, dy, dz) (lexicographically
+// positive in (dz, dy, dx), or zero).
+__device__ __forceinline__ int fwd_index(int dx, int dy, int dz) {
+  return dz == 0 ? (dy == 0 ? dx : 3 + dx) : 9 + 3 * dy + dx;
+}
+
+struct FmArgs {
+  const double4* sorted;
+  const int32_t* start;
+  const double* pos;
+  uint32_t* fmask;  // [N][14]
+  int32_t* fm_ok;   // [C]
+  int32_t nx, ny, nz;
+  double side[3];
+  double box[3];
+  float lo2, hi2;
+  double rc2;
+};
+
+__global__ __launch_bounds__(256) void k_fmask(FmArgs a) {
+  __shared__ float4 sp[FM_CAP];
+  __shared__ int32_t cst[FM_CELLS + 1];  // staged start of each staged cell
+  __shared__ int32_t cgs[FM_CELLS];      // sorted start of each staged cell
+  const int tid = threadIdx.x;
+  const int nseg = (a.nx + FM_G - 1) / FM_G;
+  const int g = blockIdx.x;
+  const int seg = g % nseg, y = (g / nseg) % a.ny, z = g / (nseg * a.ny);
+  const int x0 = seg * FM_G;
+  const int nown = (a.nx - x0 < FM_G) ? a.nx - x0 : FM_G;  // own cells x0 .. x0 + nown - 1
+  // staged cell (r, c): row r (dy, dz), column c -> x = x0 - 1 + c
+  if (tid < FM_CELLS) {
+    const int r = tid / FM_W, c = tid % FM_W;
+    const int dy = (r == 0) ? 0 : (r == 1 ? 1 : r - 3), dz = (r < 2) ? 0 : 1;
+    int cx = x0 - 1 + c, cy = y + dy, cz = z + dz;
+    cx = (cx % a.nx + a.nx) % a.nx;
+    cy = (cy % a.ny + a.ny) % a.ny;
+    cz = (cz % a.nz + a.nz) % a.nz;
+    const int cell = (cz * a.ny + cy) * a.nx + cx;
+    const int s0 = a.start[cell];
+    cgs[tid] = s0;
+    cst[tid + 1] = a.start[cell + 1] - s0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    cst[0] = 0;
+    for (int q = 0; q < FM_CELLS; ++q) cst[q + 1] += cst[q];
+  }
+  __syncthreads();
+  const int M = cst[FM_CELLS];
+  const bool fits = M <= FM_CAP;
+  // own cells' validity: staged in full and at most 32 molecules each
+  if (tid < nown) {
+    const int pop = cst[tid + 2] - cst[tid + 1];
+    a.fm_ok[(z * a.ny + y) * a.nx + x0 + tid] = (fits && pop <= 32) ? 1 : 0;
+  }
+  if (!fits) return;  // uniform
+  // stage FP32 positions in the frame of own cell x0's centre
+  for (int m = tid; m < M; m += 256) {
+    int q = 0;  // staged cell of m: the last q with cst[q] <= m
+    for (int step = 32; step > 0; step >>= 1)
+      if (q + step < FM_CELLS && cst[q + step] <= m) q += step;
+    const int r = q / FM_W, c = q % FM_W;
+    const double ox = (double)(c - 1) * a.side[0];
+    const double oy = (double)((r == 0) ? 0 : (r == 1 ? 1 : r - 3)) * a.side[1];
+    const double oz = (double)((r < 2) ? 0 : 1) * a.side[2];
+    const double4 v = a.sorted[cgs[q] + (m - cst[q])];
+    sp[m] = make_float4((float)(v.x + ox), (float)(v.y + oy), (float)(v.z + oz), 0.f);
+  }
+  __syncthreads();
+  // lanes = (own molecule, forward cell) pairs
+  const int own0 = cst[1], nmol = cst[1 + nown] - own0;
+  for (int L = tid; L < 14 * nmol; L += 256) {
+    const int ai = L / 14, k = L - 14 * ai;
+    const int am = own0 + ai;  // staged index of the molecule
+    int ca = 1;
+    while (cst[ca + 1] <= am) ++ca;  // its staged cell (row 0)
+    if (cst[ca + 1] - cst[ca] > 32) continue;
+    int dx, dy, dz;
+    if (k == 0) {
+      dx = dy = dz = 0;
+    } else if (k == 1) {
+      dx = 1; dy = 0; dz = 0;
+    } else if (k < 5) {
+      dx = k - 3; dy = 1; dz = 0;
+    } else {
+      dx = (k - 5) % 3 - 1; dy = (k - 5) / 3 - 1; dz = 1;
+    }
+    const int rb = (dz == 0) ? dy : 3 + dy;  // staged row of (dy, dz)
+    const int cb = rb * FM_W + ca + dx;
+    const int b0 = cst[cb], pop = cst[cb + 1] - b0;
+    if (pop > 32) continue;
+    const float4 pa = sp[am];
+    const int t0 = (k == 0) ? am - cst[ca] + 1 : 0;
+    uint32_t word = 0u, maybe = 0u;  // inside; inside the guard band
+    for (int t = t0; t < pop; ++t) {
+      const float4 pb = sp[b0 + t];
+      const float ex = pa.x - pb.x, ey = pa.y - pb.y, ez = pa.z - pb.z;
+      const float r2 = ex * ex + ey * ey + ez * ez;
+      word |= (r2 < a.lo2 ? 1u : 0u) << t;
+      maybe |= (r2 < a.hi2 ? 1u : 0u) << t;
+    }
+    maybe &= ~word;
+    while (maybe) {  // the exact decision (oracle expression) inside the band
+      const int t = __builtin_ctz(maybe);
+      maybe &= maybe - 1u;
+      const int ia = (int)a.sorted[cgs[ca] + (am - cst[ca])].w;
+      const int ib = (int)a.sorted[cgs[cb] + t].w;
+      if (exact_r2(a.pos, ia, ib, a.box[0], a.box[1], a.box[2]) < a.rc2) word |= 1u << t;
+    }
+    a.fmask[(size_t)(cgs[ca] + (am - cst[ca])) * 14 + k] = word;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fast tiers: at most 64*NW molecules per block (NW = 2: 128, NW = 4: 256).
+// Upper-triangle pair masks are built one wave per row.  One pass over the
+// mask words lists the upper pairs (PCAP at most) and the upper pairs the
+// block owns (PCAP/2 at most).  One pass over the pairs forms each pair's
+// owned third molecules K(i,j) = mask_i & mask_j & allowed(code_i & code_j)
+// word by word, counts the work items per size class and lists the non-empty
+// (pair, word) entries; a second pass over only those entries cuts each K
+// word into items of at most NCLS third molecules and places them, largest
+// class first, at slots taken from per-class LDS cursors.  Placement order
+// within a class does not matter: every force and energy term is summed as a
+// fixed-point integer.
 // ---------------------------------------------------------------------------
 // x in units of 2^-32, rounded to nearest, as a two's-complement 64-bit
 // value, for |x| < FAST_LIMIT (the caller checks the bound): adding 1.5 * 2^20
@@ -372,68 +514,40 @@ __device__ __forceinline__ void add_fix_m(u64* ax, u64* ay, u64* az, int m, doub
   atomicAdd(&az[m], to_fix_m(z));
 }
 
-// Work items hold at most NCLS third molecules: a K word of more bits is
-// cut into runs of NCLS set bits, lowest first, and a shorter last run, so
-// that the items of a wave have near-equal sizes.  Items are sorted by
-// popcount (class 1..NCLS); per-thread class counts are packed six 10-bit
-// fields to a word, which cannot overflow once the block's item total is
-// below 1024.
+// Work items hold at most NCLS third molecules: a K word of more bits is cut
+// into runs of NCLS set bits, lowest first, and a shorter last run, so that
+// the items of a wave have near-equal sizes.
 constexpr int NCLS = 12;
-struct Cls {  // classes 1-6 in v0, 7-12 in v1
-  u64 v0 = 0ull, v1 = 0ull;
-  __device__ void add(int c, u64 d) {
-    const int f = c - 1;
-    const bool up = f >= 6;
-    const u64 x = d << (10 * (up ? f - 6 : f));
-    v0 += up ? 0ull : x;
-    v1 += up ? x : 0ull;
-  }
-  __device__ int get(int c) const {
-    const int f = c - 1;
-    const bool up = f >= 6;
-    return (int)(((up ? v1 : v0) >> (10 * (up ? f - 6 : f))) & 0x3ffull);
-  }
-};
 
-template <int PCAP, int KCAP>
-struct LdsFast {
-  static constexpr int MAXB = 128;
-  static constexpr int NW = 2;
-  static constexpr int OCAP = PCAP / 2;
+// Pairs (i, j), i before j, whose corner codes can own a third molecule:
+// bit c' of PAIR_OK[c] is set iff some corner k >= c' (the third comes after
+// j, corner by corner) has k & c & c' == 0.  Rows of corners 4-7 own none.
+__device__ __forceinline__ uint32_t pair_ok(int c) {
+  return c < 4 ? ((0x383C7EFFu >> (8 * c)) & 0xffu) : 0u;
+}
+
+template <int NW, int PCAP, int KCAP>
+struct LdsTier {
+  static constexpr int MAXB = 64 * NW;
   BlockHead h;
   float4 sp[MAXB];   // FP32 coordinates, .w = residual of x
   float2 slo[MAXB];  // residuals of y and z
   u64 ax[MAXB], ay[MAXB], az[MAXB];
   alignas(16) u64 mask[MAXB * NW];  // bits j > i only
   u64 allow[8 * NW];
-  union {
-    uint16_t olist[OCAP];  // i | j << 7, upper pairs the block owns (lists and LJ phases)
-    struct {
-      u64 kset[KCAP];       // K bits of each work item, sorted by popcount (from the compaction on)
-      uint16_t kmeta[KCAP];  // i | j << 7 | h << 14 of the same items: bit 0 of K is molecule j + 1 + 64 h
-    };
-  };
-  u64 cntw[NWAVE][2];  // per-wave item counts per class (10-bit fields)
-  int32_t nitw[NWAVE];  // per-wave item totals
-  int32_t cnt2[2][NWAVE];
-  long long cnt2e[NWAVE];
-  uint16_t plist[PCAP];  // i | j << 7, all upper pairs
+  u64 ucol[4 * NW];      // bits j of corners c' with pair_ok(c) bit c', rows c < 4
+  uint16_t plist[PCAP];  // i | j << 8: owned upper pairs, then the others that can own a third molecule
+  u64 kset[KCAP];         // third molecules of each item (bits of word w)
+  uint16_t kmeta[KCAP];   // q | w << 13: pair plist[q], mask word w
+  uint16_t nelist[KCAP];  // the same for every non-empty K word
+  u64 tot[4][16];            // block totals in 16 slots (by lane): e_lj', w_lj', e_atm' (2^-32 units), LJ pairs
+  int32_t ccnt[NCLS + 1];    // items per class
+  int32_t cfull[16];         // items of NCLS third molecules, in 16 slots (by lane)
+  int32_t cursor[NCLS + 1];
+  int32_t nne;  // entries of nelist
+  int32_t cnt2[NWAVE];
   uint8_t scode[MAXB];
 };
-
-// K(i,j) shifted down so that bit 0 is molecule j + 1: the first item holds
-// molecules j+1 .. j+64, the second j+65 .. (at most 127).  Row j of the
-// masks has bits above j only, so no bit at or below j is dropped.
-__device__ __forceinline__ void k_items(u64 K0, u64 K1, int j, u64& lo, u64& hi) {
-  const int s = j + 1;  // 1 .. 128
-  if (s >= 64) {
-    lo = s < 128 ? K1 >> (s - 64) : 0ull;
-    hi = 0ull;
-  } else {
-    lo = (K0 >> s) | (K1 << (64 - s));
-    hi = K1 >> s;
-  }
-}
 
 // One ATM triplet of the pair (i, j) with third molecule k, in FP32, for the
 // per-pair accumulation of the fast path.  With c_x, c_y, c_z as in
@@ -484,12 +598,12 @@ __device__ __forceinline__ void atm_third(const float4 pi, const float4 pj, cons
   q.mx = fmaxf(q.mx, fmaxf(fabsf(fkx), fmaxf(fabsf(fky), fabsf(fkz))));
 }
 
-template <int PCAP, int KCAP>
-__device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L) {
-  constexpr int MAXB = 128, NW = 2, OCAP = PCAP / 2;
-  static_assert(WG == MAXB * NW, "one thread per mask word");
-  static_assert(KCAP < 1024, "item counts are packed in 10-bit fields");
-  static_assert(PCAP <= 16 * WG, "two tag bits per pair round in one word");
+template <int NW, int PCAP, int KCAP>
+__device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>& L) {
+  constexpr int MAXB = 64 * NW;
+  constexpr int WPT = MAXB * NW / WG;  // mask words per thread in the list pass
+  static_assert(MAXB * NW % WG == 0 && WPT >= 1, "whole mask words per thread");
+  static_assert(KCAP < 65536 && PCAP <= 8192 && PCAP < 65536, "16-bit counts and 13-bit pair indices");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool do_lj = (a.terms & ATM3_TERM_LJ) != 0;
   const bool do_atm = (a.terms & ATM3_TERM_ATM) != 0;
@@ -497,92 +611,127 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
   const int n = block_cells(a, b, L.h);
   if (n > MAXB) return false;
   block_stage(a, L.h, n, nullptr, L.sp, L.slo, L.ax, L.ay, L.az, L.scode, nullptr, nullptr);
+  if (tid == 0) L.nne = 0;
+  if (tid <= NCLS) L.ccnt[tid] = 0;
+  if (tid < 64) L.tot[tid >> 4][tid & 15] = 0ull;
+  if (tid < 16) L.cfull[tid] = 0;
+  const bool use_fm = (L.h.okc[0] & L.h.okc[1] & L.h.okc[2] & L.h.okc[3] & L.h.okc[4] & L.h.okc[5] &
+                       L.h.okc[6] & L.h.okc[7]) != 0;
+  if (use_fm)
+    for (int q = tid; q < MAXB * NW; q += WG) L.mask[q] = 0ull;
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
+  for (int item = wave; item < 4 * NW; item += NWAVE) {  // ucol[c][w], c < 4
+    const int c = item / NW, w = item % NW;
+    const int j = 64 * w + lane;
+    const bool ok = (j < n) && ((pair_ok(c) >> L.scode[j]) & 1u);
+    const u64 bits = __ballot(ok);
+    if (lane == 0) L.ucol[item] = bits;
+  }
 
-  // 2. upper-triangle mask words, one wave per row (rows wave, wave + 4, ...).
-  //    Lanes past the last molecule hold a far-away position, so only the
-  //    triangle (j > i) has to be masked.  Lane l holds molecules l and
-  //    64 + l in registers; a row's position is read from them with
-  //    readlane (scalar registers), which keeps this phase off the LDS.
-  {
+  // 2. upper-triangle mask words.  When every corner cell has forward-shell
+  //    words (k_fmask), row i of corner o is assembled from the words of the
+  //    corners o' >= o: their offsets o' - o are forward offsets, and corner
+  //    o' occupies staged positions cbase[o'] ...
+  if (use_fm) {
+    // one task per (row i, corner o2 >= corner of i): its word lands at
+    // bits cbase[o2] ... of row i (LDS OR into the zeroed rows)
+    for (int q = tid; q < 8 * n; q += WG) {
+      const int i = q >> 3, o2 = q & 7, o = L.scode[i];
+      if (o2 < o) continue;
+      const int dx = (o2 & 1) - (o & 1), dy = ((o2 >> 1) & 1) - ((o >> 1) & 1), dz = (o2 >> 2) - (o >> 2);
+      const u64 wd = a.fmask[(size_t)(L.h.cstart[o] + (i - L.h.cbase[o])) * 14 + fwd_index(dx, dy, dz)];
+      if (!wd) continue;
+      const int cb = L.h.cbase[o2], wq = cb >> 6, sh = cb & 63;
+      atomicOr(&L.mask[i * NW + wq], wd << sh);
+      if (sh > 32 && wq + 1 < NW) atomicOr(&L.mask[i * NW + wq + 1], wd >> (64 - sh));
+    }
+  } else {
+    //  ... else one wave per row (rows wave, wave + 4, ...).  Lane l holds
+    //  molecules l + 64 w in registers (a far-away position past the last
+    //  molecule); a row's position is read from them with readlane (scalar
+    //  registers), which keeps this phase off the LDS.
     const float4 far4 = make_float4(1e18f, 1e18f, 1e18f, 0.f);
-    const float4 pj0 = (lane < n) ? L.sp[lane] : far4;
-    const float4 pj1 = (64 + lane < n) ? L.sp[64 + lane] : far4;
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const int n0 = n < 63 ? n : 63;  // rows with bits in word 0
-    const bool two = n > 64;
+    float4 pj[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) pj[w] = (64 * w + lane < n) ? L.sp[64 * w + lane] : far4;
     auto rl = [](const float4 v, int l) {  // l wave-uniform
       return make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)),
                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.z), l)), 0.f);
     };
-    auto put = [&](int i, u64 b0, u64 b1) {
-      if (lane == 0) *reinterpret_cast<ulonglong2*>(&L.mask[i * NW]) = make_ulonglong2(b0, b1);
-    };
-    auto row2 = [&](int i, const float4 pi) {
-      const float r0 = dist2f(pi, pj0);
-      const float r1 = two ? dist2f(pi, pj1) : 1e30f;
-      const u64 tri = ~0ull << (i + 1);
-      u64 b0 = __ballot(r0 < a.lo2) & tri;
-      u64 b1 = __ballot(r1 < a.lo2);
-      const u64 m0 = __ballot(r0 < a.hi2) & tri & ~b0;
-      const u64 m1 = __ballot(r1 < a.hi2) & ~b1;
-      if (m0 | m1) {
-        b0 |= exact_bits(a, i, 0, m0, L.h, L.scode);
-        b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    for (int i = wv; i < n; i += NWAVE) {
+      const int wi = i >> 6, li = i & 63;
+      float4 pi = rl(pj[0], li);
+#pragma unroll
+      for (int w = 1; w < NW; ++w)
+        if (w == wi) pi = rl(pj[w], li);
+      u64 words[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        words[w] = 0ull;
+        if (w < wi) continue;
+        const float r2 = dist2f(pi, pj[w]);
+        const u64 tri = (w > wi) ? ~0ull : (li == 63 ? 0ull : (~0ull << (li + 1)));
+        u64 bits = __ballot(r2 < a.lo2) & tri;
+        const u64 maybe = __ballot(r2 < a.hi2) & tri & ~bits;
+        if (maybe) bits |= exact_bits(a, i, w, maybe, L.h, L.scode);
+        words[w] = bits;
       }
-      put(i, b0, b1);
-    };
-    int i = wv;
-    for (; i + NWAVE < n0; i += 2 * NWAVE) {  // two rows per pass for overlap
-      const float4 pa = rl(pj0, i), pb = rl(pj0, i + NWAVE);
-      row2(i, pa);
-      row2(i + NWAVE, pb);
+      if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; w += 2)
+          *reinterpret_cast<ulonglong2*>(&L.mask[i * NW + w]) = make_ulonglong2(words[w], words[w + 1]);
+      }
     }
-    for (; i < n0; i += NWAVE) row2(i, rl(pj0, i));
-    for (; i < n; i += NWAVE) {  // rows 63.. have bits in word 1 only
-      const float4 pi = i < 64 ? rl(pj0, i) : rl(pj1, i - 64);
-      const float r1 = dist2f(pi, pj1);
-      const u64 tri = ~0ull << (i - 63);
-      u64 b1 = __ballot(r1 < a.lo2) & tri;
-      const u64 m1 = __ballot(r1 < a.hi2) & tri & ~b1;
-      if (m1) b1 |= exact_bits(a, i, 1, m1, L.h, L.scode);
-      put(i, 0ull, b1);
-    }
-    for (; i < MAXB; i += NWAVE) put(i, 0ull, 0ull);
+    for (int i = n + wv; i < MAXB; i += NWAVE)
+      if (lane < NW) L.mask[i * NW + lane] = 0ull;
   }
   __syncthreads();
 
-  // 3. pair lists: thread t lists the bits of mask word t (row t / 2); the
-  //    two list offsets come from one scan of (count | owned count << 16)
+  // 3. pair list: thread t lists the bits of mask words t, t + WG, ...; the
+  //    pairs the block owns (corner codes AND to 0, LJ and ATM) come first,
+  //    then the other pairs that can own a third molecule (ATM only); both
+  //    offsets come from one scan of (owned count | other count << 16)
   int np, no;
   {
-    const int ri = tid >> 1, rw = tid & 1;
-    u64 wb = L.mask[tid];
-    u64 wo = (ri < n) ? (wb & L.allow[L.scode[ri] * NW + rw]) : 0ull;
-    const int packed = __popcll(wb) | (__popcll(wo) << 16);
+    u64 wo[WPT], wn[WPT];
+    int packed = 0;
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const int wd = tid + WG * k, ri = wd / NW, rw = wd % NW;
+      const u64 m = L.mask[wd];
+      const int ci = (ri < n) ? L.scode[ri] : 4;
+      wo[k] = (ri < n) ? (m & L.allow[ci * NW + rw]) : 0ull;
+      wn[k] = (ci < 4) ? (m & L.ucol[ci * NW + rw] & ~wo[k]) : 0ull;
+      packed += __popcll(wo[k]) | (__popcll(wn[k]) << 16);
+    }
     const int incl = wave_incl_scan(packed);
-    if (lane == 63) L.cnt2[0][wave] = incl;
+    if (lane == 63) L.cnt2[wave] = incl;
     __syncthreads();
     int pre = incl - packed, tot = 0;
     for (int w = 0; w < NWAVE; ++w) {
-      const int v = L.cnt2[0][w];
+      const int v = L.cnt2[w];
       if (w < wave) pre += v;
       tot += v;
     }
-    np = tot & 0xffff;
-    no = tot >> 16;
-    if (np > PCAP || no > OCAP) return false;  // uniform: block totals
-    int p = pre & 0xffff, o = pre >> 16;
-    const int jb = 64 * rw;
-    while (wb) {
-      L.plist[p++] = (uint16_t)(ri | ((jb + __builtin_ctzll(wb)) << 7));
-      wb &= wb - 1ull;
-    }
-    while (wo) {
-      L.olist[o++] = (uint16_t)(ri | ((jb + __builtin_ctzll(wo)) << 7));
-      wo &= wo - 1ull;
+    no = tot & 0xffff;
+    np = no + (tot >> 16);
+    if (np > PCAP) return false;  // uniform: block totals
+    int o = pre & 0xffff, p = no + (pre >> 16);
+#pragma unroll
+    for (int k = 0; k < WPT; ++k) {
+      const int wd = tid + WG * k, ri = wd / NW, jb = 64 * (wd % NW);
+      u64 x = wo[k], y = wn[k];
+      while (x) {
+        L.plist[o++] = (uint16_t)(ri | ((jb + __builtin_ctzll(x)) << 8));
+        x &= x - 1ull;
+      }
+      while (y) {
+        L.plist[p++] = (uint16_t)(ri | ((jb + __builtin_ctzll(y)) << 8));
+        y &= y - 1ull;
+      }
     }
   }
   __syncthreads();
@@ -590,182 +739,140 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
   double e_lj = 0.0, w_lj = 0.0;
   long long n_pair = 0;
   int far = 0;  // a value beyond FAST_LIMIT: the block goes to the general path
-  // 3a. LJ over the owned pairs (contiguous chunk per thread, FP64; thread
-  //     tid takes chunk 37 tid mod WG, so that neighbouring lanes flush F_i of
-  //     different rows)
-  if (do_lj) {
-    const int mo = (no + WG - 1) / WG;
-    const int ch = (tid * 37) & (WG - 1);
-    const int o0 = ch * mo < no ? ch * mo : no;
-    const int o1 = o0 + mo < no ? o0 + mo : no;
-    int cur = -1;
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int q = o0; q < o1; ++q) {
-      const int e = L.olist[q];
-      const int i = e & 127, j = e >> 7;
-      if (i != cur) {
-        if (cur >= 0) add_fix_m(L.ax, L.ay, L.az, cur, fx, fy, fz, &far);
-        cur = i;
-        fx = fy = fz = 0.0;
-      }
-      const float4 hi = L.sp[i], hj = L.sp[j];
-      const float2 li = L.slo[i], lj = L.slo[j];
-      const double ex = ((double)hi.x - (double)hj.x) + ((double)hi.w - (double)hj.w);
-      const double ey = ((double)hi.y - (double)hj.y) + ((double)li.x - (double)lj.x);
-      const double ez = ((double)hi.z - (double)hj.z) + ((double)li.y - (double)lj.y);
-      const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
-      fx += f * ex;
-      fy += f * ey;
-      fz += f * ez;
-      add_fix_m(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &far);
-    }
-    if (cur >= 0) add_fix_m(L.ax, L.ay, L.az, cur, fx, fy, fz, &far);
-    n_pair = o1 - o0;
-  }
 
-  // 3b. per pair (pairs pq, pq + WG, ...): K(i,j) as one or two
-  //     single-word runs (k_items), cut into items of at most NCLS bits;
-  //     each thread counts its items per popcount class
-  int mytr = 0, myit = 0;
-  uint32_t tags = 0u;  // bit 2r (2r + 1): the thread's pair of round r has a low (high) run
-  Cls cc;
-  // thread tid takes pairs pq + WG r with pq = 37 tid mod WG: neighbouring
-  // threads, whose items end up in neighbouring slots and lanes, then hold
-  // pairs of different rows, whose K overlap less (fewer same-address F_k
-  // atomics)
-  const int pq = (tid * 37) & (WG - 1);
-  if (do_atm) {
-    for (int q = pq, r = 0; q < np; q += WG, ++r) {
+  int ntr = 0, mytr = 0, myfull = 0;
+  // 4a. per pair q (lanes = pairs, rounds of WG): the LJ term of the owned
+  //     pairs (q < no; FP64 on the coordinates with their residuals), and
+  //     each non-zero word of K(i,j) as an entry of nelist, its items
+  //     counted per size class
+  // lane tid takes pair q0 + (37 tid mod WG): neighbouring lanes then hold
+  // pairs of different rows (the list is row by row), whose F_i atomics do
+  // not collide on one address
+  const int nq = do_atm ? np : no;
+  const int qp = (tid * 37) & (WG - 1);
+  for (int q0 = 0; q0 < nq; q0 += WG) {  // uniform trip count
+    const int q = q0 + qp;
+    uint32_t wm = 0u;  // bit w: word w of K(i,j) is non-empty
+    if (q < nq) {
       const int e = L.plist[q];
-      const int i = e & 127, j = e >> 7;
-      const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-      u64 lo, hi;
-      k_items(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0], L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1], j,
-              lo, hi);
-      const int cl = __popcll(lo), ch = __popcll(hi);
-      mytr += cl + ch;
-      for (int h = 0; h < 2; ++h) {
-        const int c = h ? ch : cl;
-        if (!c) continue;
-        const int full = (c - 1) / NCLS;  // runs of NCLS bits, then the rest
-        cc.add(NCLS, (u64)full);
-        cc.add(c - NCLS * full, 1ull);
-        myit += full + 1;
+      const int i = e & 255, j = e >> 8;
+      if (do_lj && q < no) {
+        const float4 hi = L.sp[i], hj = L.sp[j];
+        const float2 li = L.slo[i], lj = L.slo[j];
+        const double ex = ((double)hi.x - (double)hj.x) + ((double)hi.w - (double)hj.w);
+        const double ey = ((double)hi.y - (double)hj.y) + ((double)li.x - (double)lj.x);
+        const double ez = ((double)hi.z - (double)hj.z) + ((double)li.y - (double)lj.y);
+        const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &e_lj, &w_lj);
+        add_fix_m(L.ax, L.ay, L.az, i, f * ex, f * ey, f * ez, &far);
+        add_fix_m(L.ax, L.ay, L.az, j, -f * ex, -f * ey, -f * ez, &far);
+        ++n_pair;
       }
-      tags |= (uint32_t)((cl ? 1 : 0) | (ch ? 2 : 0)) << (2 * r);
-    }
-  }
-  // 4. item offsets without atomics: a block scan of the packed counts in
-  //    thread order, classes laid out largest first; each thread's items go
-  //    to fixed slots, so the order is reproducible
-  Cls xs;
-  xs.v0 = wave_incl_scan64(cc.v0);
-  xs.v1 = wave_incl_scan64(cc.v1);
-  if (lane == 63) {
-    L.cntw[wave][0] = xs.v0;
-    L.cntw[wave][1] = xs.v1;
-  }
-  {
-    const int wt = wave_incl_scan(mytr), wi = wave_incl_scan(myit);
-    if (lane == 63) {
-      L.cnt2[1][wave] = wt;
-      L.nitw[wave] = wi;
-    }
-  }
-  __syncthreads();
-  int ne = 0;
-  for (int v = 0; v < NWAVE; ++v) ne += L.nitw[v];
-  if (ne > KCAP) return false;  // uniform: block total (KCAP < 1024)
-  Cls tt;
-  xs.v0 -= cc.v0;
-  xs.v1 -= cc.v1;
-  for (int v = 0; v < NWAVE; ++v) {
-    const u64 t0 = L.cntw[v][0], t1 = L.cntw[v][1];
-    if (v < wave) {
-      xs.v0 += t0;
-      xs.v1 += t1;
-    }
-    tt.v0 += t0;
-    tt.v1 += t1;
-  }
-  // class totals -> class starts, class NCLS first (block-uniform, scalar
-  // registers); xs becomes this thread's next slot per class
-  {
-    const u64 s0 = ((u64)__builtin_amdgcn_readfirstlane((uint32_t)(tt.v0 >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tt.v0);
-    const u64 s1 = ((u64)__builtin_amdgcn_readfirstlane((uint32_t)(tt.v1 >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tt.v1);
-    u64 b0 = 0ull, b1 = 0ull;
-    int start = 0;
-    for (int f = NCLS - 1; f >= 0; --f) {
-      const bool up = f >= 6;
-      const int sh = 10 * (up ? f - 6 : f);
-      const int tc = (int)(((up ? s1 : s0) >> sh) & 0x3ffull);
-      if (up)
-        b1 |= (u64)start << sh;
-      else
-        b0 |= (u64)start << sh;
-      start += tc;
-    }
-    xs.v0 += b0;
-    xs.v1 += b1;
-  }
-  int ntr = 0;
-  for (int w = 0; w < NWAVE; ++w) ntr += L.cnt2[1][w];
-
-  double e_atm = 0.0;
-  if (do_atm && ntr > 0) {
-    for (uint32_t tg = tags; tg;) {  // only the pairs with a non-empty K
-      const int r = __builtin_ctz(tg) >> 1;
-      tg &= ~(3u << (2 * r));
-      const int e = L.plist[pq + WG * r];
-      const int i = e & 127, j = e >> 7;
-      const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
-      u64 lo, hi;
-      k_items(L.mask[i * NW + 0] & L.mask[j * NW + 0] & al[0], L.mask[i * NW + 1] & L.mask[j * NW + 1] & al[1], j,
-              lo, hi);
-      for (int h = 0; h < 2; ++h) {
-        u64 w = h ? hi : lo;
-        const uint16_t meta = (uint16_t)(e | h << 14);
-        while (w) {
-          u64 run = w;
-          if (__popcll(w) > NCLS) {  // the lowest NCLS bits
-            u64 r = w;
+      if (do_atm) {
+        const u64* al = &L.allow[(L.scode[i] & L.scode[j]) * NW];
 #pragma unroll
-            for (int t = 0; t < NCLS; ++t) r &= r - 1ull;
-            run = w ^ r;
+        for (int w = 0; w < NW; ++w) {
+          const u64 K = L.mask[i * NW + w] & L.mask[j * NW + w] & al[w];
+          const int c = __popcll(K);
+          if (c) {
+            mytr += c;
+            const int full = (c - 1) / NCLS;  // runs of NCLS bits, then the rest
+            myfull += full;
+            atomicAdd(&L.ccnt[c - NCLS * full], 1);
+            wm |= 1u << w;
           }
-          w ^= run;
-          const int c = __popcll(run);
-          const int pos = xs.get(c);
-          xs.add(c, 1ull);
-          L.kset[pos] = run;
-          L.kmeta[pos] = meta;
         }
+      }
+    }
+    if (do_atm) {  // append the entries to nelist (offsets by a wave scan)
+      const int cnt = __popc(wm);
+      int at = atomicAdd(&L.nne, cnt);
+#pragma unroll
+      for (int w = 0; w < NW; ++w)
+        if ((wm >> w) & 1u) {
+          if (at < KCAP) L.nelist[at] = (uint16_t)(q | (w << 13));
+          ++at;
+        }
+    }
+  }
+  {  // this thread's LJ totals into the block totals (fixed point, rounded
+     // to the nearest unit, so that the many per-thread sums carry no bias;
+     // 16 slots, so that the lanes of a wave do not all add to one address)
+    int bad = 0;
+    if (e_lj != 0.0) atomicAdd(&L.tot[0][lane & 15], to_fix(e_lj + 0.5 * FIX_INV, &bad));
+    if (w_lj != 0.0) atomicAdd(&L.tot[1][lane & 15], to_fix(w_lj + 0.5 * FIX_INV, &bad));
+    if (n_pair) atomicAdd(&L.tot[3][lane & 15], (u64)n_pair);
+    far |= bad;
+  }
+  __syncthreads();  // the LJ phase's chunks are done
+  if (do_atm) {
+    // class totals (block-uniform) and the class cursors, largest first
+    const int wt = wave_incl_scan(mytr);
+    if (lane == 63) L.cnt2[wave] = wt;
+    if (myfull) atomicAdd(&L.cfull[lane & 15], myfull);
+    __syncthreads();
+    for (int v = 0; v < NWAVE; ++v) ntr += L.cnt2[v];
+    int ne = 0;
+    for (int c = NCLS; c >= 1; --c) {
+      int cnt = L.ccnt[c];
+      if (c == NCLS)
+        for (int s = 0; s < 16; ++s) cnt += L.cfull[s];
+      if (tid == c) L.cursor[c] = ne;
+      ne += cnt;
+    }
+    const int nne = L.nne;
+    if (ne > KCAP || nne > KCAP) return false;  // uniform: block totals
+    __syncthreads();
+
+    // 4b. items: the non-empty K words (lanes = entries, entry 37 tid mod WG
+    //     + WG r, so that neighbouring lanes hold pairs of different rows,
+    //     whose K overlap less: fewer same-address F_k atomics later) cut
+    //     into runs and placed at their class cursors
+    for (int r = 0; WG * r < nne; ++r) {
+      const int p = ((tid * 37) & (WG - 1)) + WG * r;
+      if (p >= nne) continue;
+      const int v = L.nelist[p];
+      const int e = L.plist[v & 8191], w = v >> 13;
+      const int i = e & 255, j = e >> 8;
+      u64 K = L.mask[i * NW + w] & L.mask[j * NW + w] & L.allow[(L.scode[i] & L.scode[j]) * NW + w];
+      while (K) {
+        u64 run = K;
+        if (__popcll(K) > NCLS) {  // the lowest NCLS bits
+          u64 x = K;
+#pragma unroll
+          for (int t = 0; t < NCLS; ++t) x &= x - 1ull;
+          run = K ^ x;
+        }
+        K ^= run;
+        const int slot = atomicAdd(&L.cursor[__popcll(run)], 1);
+        L.kset[slot] = run;
+        L.kmeta[slot] = (uint16_t)v;
       }
     }
     __syncthreads();
 
     // 5. ATM: each thread takes whole items, item tid + WG r in round r, so
-    //    the 64 items of a wave have similar popcounts and finish together;
-    //    the pair's sums stay in registers for an item and only F_k is
-    //    added per triplet; the item's energy is added in fixed point.  All
-    //    of it is converted with to_fix_m; a value beyond its range sends
-    //    the block to the general path.
+    //    the 64 items of a wave have similar sizes and finish together; the
+    //    pair's sums stay in registers for an item and only F_k is added per
+    //    triplet; the item's energy is added in fixed point.  All of it is
+    //    converted with to_fix_m; a value beyond its range sends the block to
+    //    the general path.
     u64 eacc = 0ull;
     float tmx = 0.f;  // max |F_k|, and sums of the item totals (NaN-propagating)
     for (int p = tid; p < ne; p += WG) {
-      const int m = L.kmeta[p];
-      const int ci = m & 127, cj = (m >> 7) & 127;
-      const int base = cj + 1 + ((m >> 8) & 64);  // j + 1 + 64 h
+      const int v = L.kmeta[p];
+      const int e = L.plist[v & 8191];
+      const int ci = e & 255, cj = e >> 8;
+      const int base = 64 * (v >> 13);
       const float4* spk = L.sp + base;
       u64* axk = L.ax + base;
       u64* ayk = L.ay + base;
       u64* azk = L.az + base;
-      // odd lanes walk K from the top: neighbouring lanes often hold pairs
-      // of one row, whose K overlap, and would otherwise hit the same F_k
-      // address in the same instruction
-      const int flip = (lane & 1) ? 63 : 0;
+      // items of pairs with an odd j walk K from the top: pairs of one row
+      // have overlapping K, and lanes holding them would otherwise hit the
+      // same F_k address in the same instruction.  The direction is a
+      // property of the item, not of the lane it lands on, so that every
+      // item's FP32 sums are the same from run to run
+      const int flip = (cj & 1) ? 63 : 0;
       u64 K = L.kset[p];
       if (flip) K = __builtin_bitreverse64(K);
       const float4 pi = L.sp[ci], pj = L.sp[cj];
@@ -796,19 +903,27 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsFast<PCAP, KCAP>& L)
       eacc += to_fix_m(q.eu);
     }
     far |= !(tmx < FAST_LIMIT);
-    // exact block total of the energy; thread 0 carries it into the flush
-    const long long ew = wave_sum_ll((long long)eacc);
-    __syncthreads();  // every wave is past its last read of cnt2
-    if (lane == 0) L.cnt2e[wave] = ew;
-    __syncthreads();
-    if (tid == 0) {
-      long long et = 0;
-      for (int w = 0; w < NWAVE; ++w) et += L.cnt2e[w];
-      e_atm = from_fix((u64)et);
-    }
+    if (eacc) atomicAdd(&L.tot[2][lane & 15], eacc);
   }
   if (__syncthreads_or(far)) return false;  // uniform
-  block_flush(a, b, n, L.scode, nullptr, L.ax, L.ay, L.az, L.h, e_lj, w_lj, e_atm, n_pair, do_atm ? ntr : 0, 0);
+  // per-corner partial forces (each (corner, molecule) written by exactly
+  // one block) and the block's totals
+  const int N = a.ntot;
+  for (int q = tid; q < n; q += WG) {
+    const int o = L.scode[q], s = L.h.cstart[o] + (q - L.h.cbase[o]);
+    a.fpart[(int64_t)(o * 3 + 0) * N + s] = L.ax[q];
+    a.fpart[(int64_t)(o * 3 + 1) * N + s] = L.ay[q];
+    a.fpart[(int64_t)(o * 3 + 2) * N + s] = L.az[q];
+  }
+  if (tid < 4) {
+    u64 s = 0ull;
+    for (int k = 0; k < 16; ++k) s += L.tot[tid][k];
+    if (tid < 3)
+      a.blkd[3 * (int64_t)b + tid] = from_fix(s);
+    else
+      a.blki[2 * (int64_t)b + 0] = (int32_t)s;
+  }
+  if (tid == 0) a.blki[2 * (int64_t)b + 1] = do_atm ? ntr : 0;
   return true;
 }
 
@@ -1019,11 +1134,11 @@ __device__ bool do_block_big(const ForceArgs& a, int b, LdsBig<NW, PCAP, TCAP>& 
 // one XCD map to consecutive base cells so neighbouring blocks share its L2.
 template <int PCAP, int KCAP>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_block(ForceArgs a) {
-  __shared__ LdsFast<PCAP, KCAP> L;
+  __shared__ LdsTier<2, PCAP, KCAP> L;
   const int per = (a.ncells + 7) / 8;
   const int b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if ((blockIdx.x >> 3) >= per || b >= a.ncells) return;
-  if (!do_block_fast<PCAP, KCAP>(a, b, L)) {
+  if (!do_block_fast<2, PCAP, KCAP>(a, b, L)) {
     if (threadIdx.x == 0) {
       const int q = atomicAdd(&a.defer[0], 1);
       a.defer[2 + q] = b;
@@ -1031,17 +1146,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
   }
 }
 
-// The queued blocks again through the same path with room for the pair and
-// item counts of dense liquids (about 0.8 and above); what still does not
-// fit is queued (defer[ncells + 2..]) for k_block_big.
+// The queued blocks again, with four mask words per row (up to 256
+// molecules: dense liquids, or cutoffs up to about 3.2 at the benchmark
+// density) and room for more pairs and items; what still does not fit is
+// queued (defer[ncells + 2..]) for k_block_big.
 template <int PCAP, int KCAP>
 __global__ __launch_bounds__(WG) void k_block_wide(ForceArgs a) {
-  __shared__ LdsFast<PCAP, KCAP> L;
+  __shared__ LdsTier<4, PCAP, KCAP> L;
   int32_t* q2 = a.defer + 2 + a.ncells;
   const int nq = a.defer[0];
   for (int q = blockIdx.x; q < nq; q += gridDim.x) {
     const int b = a.defer[2 + q];
-    if (!do_block_fast<PCAP, KCAP>(a, b, L)) {
+    if (!do_block_fast<4, PCAP, KCAP>(a, b, L)) {
       if (threadIdx.x == 0) {
         const int t = atomicAdd(&q2[0], 1);
         q2[1 + t] = b;
@@ -1245,12 +1361,34 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
 
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.defer, a.ncells);
   const int per = (a.ncells + 7) / 8;
+  FmArgs fa;
+  fa.sorted = a.sorted;
+  fa.start = a.start;
+  fa.pos = pos;
+  fa.fmask = (uint32_t*)ctx->buf[B_FMASK];
+  fa.fm_ok = (int32_t*)ctx->buf[B_FMOK];
+  fa.nx = a.nx;
+  fa.ny = a.ny;
+  fa.nz = a.nz;
+  for (int d = 0; d < 3; ++d) {
+    fa.side[d] = g.side[d];
+    fa.box[d] = g.box[d];
+  }
+  fa.lo2 = a.lo2;
+  fa.hi2 = a.hi2;
+  fa.rc2 = a.rc2;
+  a.fmask = fa.fmask;
+  a.fm_ok = fa.fm_ok;
+  // the wide tier loops over the queue; enough workgroups to fill the GPU
+  // when every block is queued (large cutoffs)
+  const unsigned wide_grid = (unsigned)(a.ncells < 3 * 256 ? a.ncells : 3 * 256);
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block<1536, 768>), dim3(8 * per), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL(k_fmask, dim3((unsigned)(((a.nx + FM_G - 1) / FM_G) * a.ny * a.nz)), dim3(256), 0, st, fa);
+  hipLaunchKernelGGL((k_block<1536, 640>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block_wide<2560, 1016>), dim3(256), dim3(WG), 0, st, a);
+  hipLaunchKernelGGL((k_block_wide<4096, 2048>), dim3(wide_grid), dim3(WG), 0, st, a);
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_REDUCE)) != hipSuccess) return e;

@@ -34,6 +34,8 @@ enum Buf {
   B_DEFER,        // int32 [2C+3] [0] count, [1] status, [2..C+2) queued base cells, [C+2] count, [C+3..) of the wide tier
   B_RED,          // first-stage reduction partials
   B_TILE,         // int32 per-tile sums of the cell-count scan
+  B_FMASK,        // uint32 [N][14] forward-shell pair masks (sorted order)
+  B_FMOK,         // int32 [C] the mask words of a cell were written
   // learned surrogate (atm3_surrogate.hip); slot = sorted molecule index
   B_SN_ALL,       // int32 [N]   neighbours per slot
   B_SN_UP,        // int32 [N]   neighbours with a larger slot

@@ -294,8 +294,33 @@ def test_dense_liquid_blocks_take_the_wide_tier(torch_cuda, orc):
     ref = orc.brute(pos, box, rc=RC, nu=NU)
     f, r = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU)
     assert r["status"] == 0
-    check_against(ref, f, r)
+    err = check_against(ref, f, r)
     assert r["n_candidates"] == ref.n_candidates
+    # the ATM-only error at this density (the FP32 triplet arithmetic is the
+    # part of the error that grows with density)
+    ref2 = orc.brute(pos, box, rc=RC, nu=NU, terms=2)
+    f2, r2 = gpu_eval(torch_cuda, pos, box, rc=RC, nu=NU, terms=2)
+    err2 = check_against(ref2, f2, r2, terms=2)
+    _say(f"  force err {err:.2e}, ATM only {err2:.2e}")
+
+
+@pytest.mark.parametrize("case", ["fuzz", "fcc32k"])
+def test_cutoff_3_takes_the_four_word_tier(torch_cuda, orc, case):
+    """rc = 3.0 at density 0.7-0.75: a 2x2x2 block holds about 190 molecules,
+    beyond the two-word tier, and every block goes through the four-word
+    tier (up to 256 molecules).  Whole-system parity against the oracle."""
+    rc = 3.0
+    if case == "fuzz":
+        pos, box = workloads.rsa(1400, [13.0, 13.0, 13.0], dmin=0.85, seed=workloads.SEED_BASE + 44)
+        ref = orc.brute(pos, box, rc=rc, nu=NU)
+    else:
+        pos, box = workloads.make("fcc32k")
+        ref = orc.cells(pos, box, rc=rc, nu=NU)
+    _say(f"[rc 3] {case} n={len(pos)}")
+    f, r = gpu_eval(torch_cuda, pos, box, rc=rc, nu=NU)
+    assert r["status"] == 0
+    err = check_against(ref, f, r)
+    _say(f"  force err {err:.2e}; triplets {r['n_triplets']}")
 
 
 @pytest.mark.parametrize("terms", [3, 1])
