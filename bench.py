@@ -388,7 +388,7 @@ def main():
                    "n": n, "ncell": list(r["ncell"]), "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": traffic,
-                     "kernel": "k_block (fused LJ+ATM, 2x2x2 cell blocks)",
+                     "kernel": "k_fmask + k_block (forward-shell pair masks, then fused LJ+ATM over 2x2x2 cell blocks)",
                      "flops_per_launch": flops, "avg_launch_ms": t_blk * 1e3},
         "binning_roofline": {"bound": "hbm", "achieved": BYTES_BIN * n / t_bin / 1e9, "peak": PEAK_HBM / 1e9,
                              "unit": "GB/s", "frac": BYTES_BIN * n / t_bin / PEAK_HBM, "bytes_per_molecule": BYTES_BIN,

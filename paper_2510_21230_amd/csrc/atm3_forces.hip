@@ -518,6 +518,9 @@ __device__ __forceinline__ void add_fix_m(u64* ax, u64* ay, u64* az, int m, doub
 // into runs of NCLS set bits, lowest first, and a shorter last run, so that
 // the items of a wave have near-equal sizes.
 constexpr int NCLS = 12;
+// work items of the four-word tier (2x2x2 blocks at rc 3.0 and density 0.75
+// need about 2,000, 2,500 at the 99th percentile)
+constexpr int WIDE_KCAP = 3072;
 
 // Pairs (i, j), i before j, whose corner codes can own a third molecule:
 // bit c' of PAIR_OK[c] is set iff some corner k >= c' (the third comes after
@@ -1146,17 +1149,26 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
   }
 }
 
-// The queued blocks again, with four mask words per row (up to 256
-// molecules: dense liquids, or cutoffs up to about 3.2 at the benchmark
-// density) and room for more pairs and items; what still does not fit is
-// queued (defer[ncells + 2..]) for k_block_big.
-template <int PCAP, int KCAP>
+// Four mask words per row (up to 256 molecules: dense liquids, or cutoffs
+// up to about 3.2 at the benchmark density) and room for more pairs and
+// items.  QUEUED: the blocks k_block queued, looped over by a grid that fills
+// the GPU; else every base cell, one workgroup each (spread over the XCDs
+// like k_block), for grids whose mean block is past the two-word tier.
+// What still does not fit is queued (defer[ncells + 2..]) for k_block_big.
+template <int PCAP, int KCAP, bool QUEUED>
 __global__ __launch_bounds__(WG) void k_block_wide(ForceArgs a) {
   __shared__ LdsTier<4, PCAP, KCAP> L;
   int32_t* q2 = a.defer + 2 + a.ncells;
-  const int nq = a.defer[0];
-  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-    const int b = a.defer[2 + q];
+  int nq = 1, b = 0;
+  if (QUEUED) {
+    nq = a.defer[0];
+  } else {
+    const int per = (a.ncells + 7) / 8;
+    b = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if ((blockIdx.x >> 3) >= per || b >= a.ncells) return;
+  }
+  for (int q = QUEUED ? (int)blockIdx.x : 0; q < nq; q += QUEUED ? (int)gridDim.x : 1) {
+    if (QUEUED) b = a.defer[2 + q];
     if (!do_block_fast<4, PCAP, KCAP>(a, b, L)) {
       if (threadIdx.x == 0) {
         const int t = atomicAdd(&q2[0], 1);
@@ -1379,16 +1391,22 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   fa.rc2 = a.rc2;
   a.fmask = fa.fmask;
   a.fm_ok = fa.fm_ok;
-  // the wide tier loops over the queue; enough workgroups to fill the GPU
-  // when every block is queued (large cutoffs)
-  const unsigned wide_grid = (unsigned)(a.ncells < 3 * 256 ? a.ncells : 3 * 256);
+  // the queued wide tier loops over the queue; its LDS (about 67 KB) admits
+  // two workgroups per CU, so 512 of them fill the GPU
+  const unsigned wide_grid = (unsigned)(a.ncells < 2 * 256 ? a.ncells : 2 * 256);
   hipError_t e = phase_begin(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fmask, dim3((unsigned)(((a.nx + FM_G - 1) / FM_G) * a.ny * a.nz)), dim3(256), 0, st, fa);
-  hipLaunchKernelGGL((k_block<1536, 640>), dim3(8 * per), dim3(WG), 0, st, a);
+  // a grid whose mean 2x2x2 block holds more than 112 molecules would queue
+  // a large share of its blocks: they all take the four-word tier directly
+  const bool wide_all = 8 * n > 112 * (int64_t)a.ncells;
+  if (wide_all)
+    hipLaunchKernelGGL((k_block_wide<4096, WIDE_KCAP, false>), dim3(8 * per), dim3(WG), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_block<1536, 640>), dim3(8 * per), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BLOCK)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_block_wide<4096, 2048>), dim3(wide_grid), dim3(WG), 0, st, a);
+  if (!wide_all) hipLaunchKernelGGL((k_block_wide<4096, WIDE_KCAP, true>), dim3(wide_grid), dim3(WG), 0, st, a);
   hipLaunchKernelGGL((k_block_big<8, 4096, 4096>), dim3(256), dim3(WG), 0, st, a);
   if ((e = phase_end(ctx, ATM3_PHASE_BIG)) != hipSuccess) return e;
   if ((e = phase_begin(ctx, ATM3_PHASE_REDUCE)) != hipSuccess) return e;

@@ -306,9 +306,11 @@ def test_dense_liquid_blocks_take_the_wide_tier(torch_cuda, orc):
 
 @pytest.mark.parametrize("case", ["fuzz", "fcc32k"])
 def test_cutoff_3_takes_the_four_word_tier(torch_cuda, orc, case):
-    """rc = 3.0 at density 0.7-0.75: a 2x2x2 block holds about 190 molecules,
-    beyond the two-word tier, and every block goes through the four-word
-    tier (up to 256 molecules).  Whole-system parity against the oracle."""
+    """rc = 3.0 at density 0.7-0.75: a 2x2x2 block holds about 170-190
+    molecules, beyond the two-word tier, so the four-word tier (up to 256
+    molecules) is launched over every base cell directly (the dense liquid
+    above takes it through the queue).  Whole-system parity against the
+    oracle."""
     rc = 3.0
     if case == "fuzz":
         pos, box = workloads.rsa(1400, [13.0, 13.0, 13.0], dmin=0.85, seed=workloads.SEED_BASE + 44)
