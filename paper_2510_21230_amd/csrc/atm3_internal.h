@@ -73,6 +73,7 @@ enum Buf {
   B_TPART,        // float split-K partial products
   B_ZHIST,        // uint32 [nbins] z histogram of the slab correction
   B_MDSLOT,       // atm3_result of the step in flight + step counter (graph-launched MD)
+  B_PDEFER,       // int32 [C] base cells the shell-pruned product tier handed on
   B_NBUF
 };
 

@@ -546,6 +546,10 @@ struct ProdArgs {
   double rc2;
   float lo2f, hi2f;
   double* tpart;
+  // shell-pruned tier: 1 / t1, t1^2 and rc^6 (1 + 1e-3); per base cell, 1 if
+  // k_prod_fast handed the cell on (k_prod_block skips the others)
+  float pf_inv_t1, pf_t1sq, pf_h6;
+  int32_t* pdefer;
 };
 
 struct ProdLds {
@@ -598,6 +602,13 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t b = blockIdx.x / a.splits;
   const int split = blockIdx.x % a.splits;
+  if (a.pdefer != nullptr && a.pdefer[b] == 0) {  // done by k_prod_fast
+    if (threadIdx.x < 4) {
+      a.dpart[4 * (int64_t)blockIdx.x + threadIdx.x] = 0.0;
+      a.ipart[4 * (int64_t)blockIdx.x + threadIdx.x] = 0ull;
+    }
+    return;
+  }
   const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((int64_t)a.nx * a.ny));
   constexpr int NCS = (VAR == ATM3_VARIANT_3C08) ? 8 : 14;
   // offsets of the cell set; 3c18: base, then the forward half in z-major order
@@ -795,6 +806,450 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// product cutoff, 3c08 and 3c18: shell-pruned tier
+// ---------------------------------------------------------------------------
+// Same cell sets and ownership as k_prod_block, with the third molecules
+// pruned before any triplet is evaluated.  Each triplet of a cell set is
+// enumerated once, by its designated pair: the pair with the smallest FP32
+// squared side (ties: the smaller pair key i << 8 | j, i < j, in staging
+// order).  A triplet inside the product cutoff has its shortest side inside
+// rc (x^3 <= x y z < rc^6), so the rows are the pairs within rc (a relative
+// band wider), and the third molecules k of row (i, j), squared side x, are
+// those with y = |r_ik|^2 >= x, z = |r_jk|^2 >= x and x y z < rc^6.
+// Shells: every staged squared distance D falls in one of 16 shells, shell
+// 0 below t1 = rc^2 (1 + 1e-4) / 8 and shell a >= 1 from t1 2^((a - 1) / 2)
+// up (read off the FP32 exponent and mantissa of D / t1), held as four bit
+// planes per row and mask word.  A lane per row keeps the k whose shells
+// with i and with j are both at least x's and whose shell lower bounds allow
+// x y z < rc^6 (1 + 1e-3): with y >= t1 2^((a - 1) / 2) and z likewise that
+// is a + b <= 1 + ceil(2 log2(rc^6 (1 + 1e-3) / (t1^2 x))), a bit-sliced add
+// and compare over 64 molecules at once.  The kept set holds every triplet
+// inside the cutoff and about half as many again on the benchmark fluid.
+// It is cut into work items of at most PF_NCLS molecules, counting-sorted by
+// size, and a lane per item takes the designation test, the product test
+// (FP32 with a relative band, the oracle's FP64 test inside it and for sides
+// under a quarter cell) and the ATM force on all three molecules (eq.
+// forcepairs: the pair's two forces summed over its items in registers),
+// in 2^-32 fixed point, as is the energy.  Blocks beyond the tier (more
+// molecules, rows or items than it holds) set their flag in `pdefer` and
+// k_prod_block evaluates them.
+constexpr int PF_WG = 256;
+constexpr int PF_NCLS = 12;                    // third molecules per work item at most
+constexpr int PF_NSH = 16;                     // shells: four bit planes
+constexpr uint32_t PF_SQRT2_MANT = 0x3504F3u;  // mantissa bits of sqrt(2) in FP32
+constexpr float PF_FIX_LIMIT = 262144.f;       // 2^18: the fixed-point conversion's range
+
+template <int NW, int PCAP, int KCAP>
+struct ProdFastLds {
+  static constexpr int MAXB = 64 * NW;
+  float4 p[MAXB];                        // block-frame position, .w = input index
+  unsigned long long pl[MAXB][NW][4];    // bit k of plane b: bit b of the shell of (i, k)
+  unsigned long long own[8][NW];         // 3c08: k with code & m == 0; 3c18: [0] base cell, [1] all
+  unsigned long long f[3][MAXB];         // ATM forces, 2^-32 units
+  uint16_t plist[PCAP];                  // rows i | j << 8, i < j
+  unsigned long long kset[KCAP];         // third molecules of an item (bits of word w)
+  uint16_t kmeta[KCAP];                  // row | w << 12
+  uint8_t code[MAXB];
+  int32_t cnt[16], base[16], cell[16];
+  int32_t ccnt[PF_NCLS + 1], cursor[PF_NCLS + 1];
+  int32_t wsum[PF_WG / 64];
+  int32_t nrows, nitems, abort;
+  unsigned long long red[PF_WG / 64][3];
+};
+
+// 2^-32 fixed point by a magic add in FP64 (|v| < 2^19; the caller checks).
+__device__ __forceinline__ unsigned long long pf_fix(float v) {
+  const double t = (double)v + 1572864.0;
+  return (unsigned long long)__double_as_longlong(t) - 0x4138000000000000ull;
+}
+
+// Shell of a squared distance d (inv_t1 = 1 / t1).
+__device__ __forceinline__ int pf_shell(float d, float inv_t1) {
+  const float u = d * inv_t1;
+  const uint32_t bits = __float_as_uint(u);
+  const int s = 1 + 2 * ((int)(bits >> 23) - 127) + ((bits & 0x7fffffu) >= PF_SQRT2_MANT ? 1 : 0);
+  return u < 1.f ? 0 : (s > PF_NSH - 1 ? PF_NSH - 1 : s);
+}
+
+// Bit-sliced comparisons with a per-lane constant c whose bits are given as
+// all-ones / zero masks m[b]: values (planes v[]) >= c, and <= c.
+template <int NB>
+__device__ __forceinline__ unsigned long long pf_ge(const unsigned long long* v, const unsigned long long* m) {
+  unsigned long long lt = 0ull, eq = ~0ull;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) {
+    lt |= eq & ~v[b] & m[b];
+    eq &= ~(v[b] ^ m[b]);
+  }
+  return ~lt;
+}
+template <int NB>
+__device__ __forceinline__ unsigned long long pf_le(const unsigned long long* v, const unsigned long long* m) {
+  unsigned long long gt = 0ull, eq = ~0ull;
+#pragma unroll
+  for (int b = NB - 1; b >= 0; --b) {
+    gt |= eq & v[b] & ~m[b];
+    eq &= ~(v[b] ^ m[b]);
+  }
+  return ~gt;
+}
+
+// Exclusive prefix over the block of one value per thread; *total gets the sum.
+__device__ __forceinline__ int pf_scan(int v, int32_t* wsum, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int s = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(s, o);
+    if (lane >= o) s += t;
+  }
+  if (lane == 63) wsum[wave] = s;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < PF_WG / 64; ++q) {
+    before += q < wave ? wsum[q] : 0;
+    all += wsum[q];
+  }
+  __syncthreads();
+  *total = all;
+  return before + s - v;
+}
+
+// RPT rows per thread and round: a round's items must fit KCAP (on the
+// benchmark fluid at most about 1,600 of 2,048 for 3c08 with 512 rows, and
+// 1,300 of 1,536 for 3c18 with 256: its first rows, those of base-cell
+// molecules, take third molecules from the whole set)
+template <int VAR, int NW, int PCAP, int KCAP, int RPT>
+__global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
+  using Lds = ProdFastLds<NW, PCAP, KCAP>;
+  constexpr int MAXB = Lds::MAXB;
+  constexpr int NCS = (VAR == ATM3_VARIANT_3C08) ? 8 : 14;
+  static_assert(PCAP <= 4096 && NW <= 4 && MAXB <= 256, "12-bit rows, 2-bit words, 8-bit molecule indices");
+  __shared__ Lds L;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ncells = (int64_t)a.nx * a.ny * a.nz;
+  const int64_t per = (ncells + 7) / 8;
+  const int64_t b = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if ((int64_t)(blockIdx.x >> 3) >= per || b >= ncells) return;
+  const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((int64_t)a.nx * a.ny));
+  auto offs = [](int q, int& dx, int& dy, int& dz) {
+    if (VAR == ATM3_VARIANT_3C08) {
+      dx = q & 1, dy = (q >> 1) & 1, dz = q >> 2;
+    } else {
+      const int t = q == 0 ? 13 : 13 + q;  // base, then the forward half of the 27-cube in z-major order
+      dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    }
+  };
+  if (tid < NCS) {
+    int dx, dy, dz;
+    offs(tid, dx, dy, dz);
+    const int ux = wrapc(bx + dx, a.nx), uy = wrapc(by + dy, a.ny), uz = wrapc(bz + dz, a.nz);
+    const int cc = (uz * a.ny + uy) * a.nx + ux;
+    L.cell[tid] = cc;
+    L.cnt[tid] = a.start[cc + 1] - a.start[cc];
+  }
+  if (tid <= PF_NCLS) L.ccnt[tid] = 0;
+  if (tid == 0) L.abort = 0;
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int q = 0; q < NCS; ++q) {
+      L.base[q] = s;
+      s += L.cnt[q];
+    }
+    L.base[NCS] = s;
+  }
+  __syncthreads();
+  const int n = L.base[NCS];
+  unsigned long long eacc = 0ull;
+  int ntr = 0, far = 0;
+  bool fits = n <= MAXB;
+  if (fits) {
+    // 1. stage the cell set (block frame: relative to the base cell's centre)
+    for (int q = wave; q < NCS; q += PF_WG / 64) {
+      int dx, dy, dz;
+      offs(q, dx, dy, dz);
+      const int t0 = a.start[L.cell[q]], m = L.cnt[q], bb = L.base[q];
+      const uint8_t code = (VAR == ATM3_VARIANT_3C08) ? (uint8_t)q : (uint8_t)(q == 0 ? 0 : 1);
+      for (int t = lane; t < m; t += 64) {
+        const double4 o = a.sorted[t0 + t];
+        L.p[bb + t] = make_float4((float)(o.x + dx * a.side[0]), (float)(o.y + dy * a.side[1]),
+                                  (float)(o.z + dz * a.side[2]), __int_as_float((int)o.w));
+        L.code[bb + t] = code;
+      }
+    }
+    for (int t = tid; t < n; t += PF_WG) L.f[0][t] = L.f[1][t] = L.f[2][t] = 0ull;
+    __syncthreads();
+    // 2. shell planes, a wave per (row, word), and the ownership masks
+    for (int task = wave; task < n * NW; task += PF_WG / 64) {
+      const int i = task / NW, w = task - (task / NW) * NW;
+      const float4 pi = L.p[i];
+      const int k = 64 * w + lane;
+      int s = 0;
+      if (k < n) {
+        const float4 pk = L.p[k];
+        s = pf_shell(sq3(make_float3(pi.x - pk.x, pi.y - pk.y, pi.z - pk.z)), a.pf_inv_t1);
+      }
+      const unsigned long long b0 = __ballot(s & 1), b1 = __ballot(s & 2), b2 = __ballot(s & 4), b3 = __ballot(s & 8);
+      if (lane < 4) L.pl[i][w][lane] = lane == 0 ? b0 : (lane == 1 ? b1 : (lane == 2 ? b2 : b3));
+    }
+    constexpr int NOWN = (VAR == ATM3_VARIANT_3C08) ? 8 : 2;
+    for (int task = wave; task < NOWN * NW; task += PF_WG / 64) {
+      const int m = task / NW, w = task - (task / NW) * NW;
+      const int k = 64 * w + lane;
+      bool okk = false;
+      if (k < n) okk = (VAR == ATM3_VARIANT_3C08) ? (L.code[k] & m) == 0 : (m == 1 || L.code[k] == 0);
+      const unsigned long long bits = __ballot(okk);
+      if (lane == 0) L.own[m][w] = bits;
+    }
+    __syncthreads();
+    // 3. rows: pairs i < j with shell <= 6 (D < t1 * 8 = rc^2 (1 + 1e-4)), a thread per molecule i
+    unsigned long long rw[NW];
+    int cnt = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      rw[w] = 0ull;
+      if (tid < n) {
+        const unsigned long long* v = L.pl[tid][w];
+        const int lo = tid - 64 * w + 1;  // bits k > tid
+        const unsigned long long gt = lo <= 0 ? ~0ull : (lo >= 64 ? 0ull : (~0ull << lo));
+        rw[w] = ~v[3] & ~(v[2] & v[1] & v[0]) & gt & L.own[VAR == ATM3_VARIANT_3C08 ? 0 : 1][w];
+        cnt += __popcll(rw[w]);
+      }
+    }
+    int nrows = 0;
+    int off = pf_scan(cnt, L.wsum, &nrows);
+    if (nrows > PCAP) {
+      fits = false;
+    } else {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        unsigned long long bits = rw[w];
+        while (bits) {
+          const int j = 64 * w + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          L.plist[off++] = (uint16_t)(tid | (j << 8));
+        }
+      }
+    }
+    __syncthreads();
+    // 4. rounds of PF_WG * RPT rows: kept third molecules, items, ATM
+    for (int r0 = 0; fits && r0 < nrows; r0 += PF_WG * RPT) {
+      unsigned long long K[RPT][NW];
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr) {
+        const int q = r0 + rr * PF_WG + tid;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) K[rr][w] = 0ull;
+        if (q >= nrows) continue;
+        const int pr = L.plist[q], i = pr & 255, j = pr >> 8;
+        const float4 pi = L.p[i], pj = L.p[j];
+        const float x = sq3(make_float3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z));
+        const int ax = pf_shell(x, a.pf_inv_t1);
+        int cmax = 31;
+        if (ax > 0) cmax = min(31, (int)ceilf(2.f * __log2f(a.pf_h6 / (a.pf_t1sq * x)) + 1e-3f) + 1);
+        unsigned long long mx[4], mc[5];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) mx[t] = ((ax >> t) & 1) ? ~0ull : 0ull;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) mc[t] = ((cmax >> t) & 1) ? ~0ull : 0ull;
+        const int ci = L.code[i], cj = L.code[j];
+        const int om = (VAR == ATM3_VARIANT_3C08) ? (ci & cj) : ((ci == 0 || cj == 0) ? 1 : 0);
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          unsigned long long vi[4], vj[4], s[5];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            vi[t] = L.pl[i][w][t];
+            vj[t] = L.pl[j][w][t];
+          }
+          // s = shell(i, k) + shell(j, k), five planes
+          unsigned long long c = 0ull;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const unsigned long long h = vi[t] ^ vj[t];
+            s[t] = h ^ c;
+            c = (vi[t] & vj[t]) | (c & h);
+          }
+          s[4] = c;
+          unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & L.own[om][w];
+          if ((i >> 6) == w) kw &= ~(1ull << (i & 63));
+          if ((j >> 6) == w) kw &= ~(1ull << (j & 63));
+          K[rr][w] = kw;
+          const int p = __popcll(kw);
+          if (p >= PF_NCLS) atomicAdd(&L.ccnt[PF_NCLS], p / PF_NCLS);
+          if (p % PF_NCLS) atomicAdd(&L.ccnt[p % PF_NCLS], 1);
+        }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int run = 0;
+        for (int c = PF_NCLS; c >= 1; --c) {  // largest items first
+          L.cursor[c] = run;
+          run += L.ccnt[c];
+        }
+        L.nitems = run;
+        if (run > KCAP) L.abort = 1;
+      }
+      __syncthreads();
+      if (L.abort) {
+        fits = false;
+        break;
+      }
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr) {
+        const int q = r0 + rr * PF_WG + tid;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          unsigned long long bits = K[rr][w];
+          while (bits) {
+            unsigned long long run = bits;
+            int c = __popcll(bits);
+            if (c > PF_NCLS) {  // the lowest PF_NCLS set bits
+              run = 0ull;
+              unsigned long long t = bits;
+              for (int u = 0; u < PF_NCLS; ++u) {
+                run |= t & (~t + 1ull);
+                t &= t - 1ull;
+              }
+              c = PF_NCLS;
+            }
+            bits ^= run;
+            const int slot = atomicAdd(&L.cursor[c], 1);
+            L.kset[slot] = run;
+            L.kmeta[slot] = (uint16_t)(q | (w << 12));
+          }
+        }
+      }
+      __syncthreads();
+      const int nitems = L.nitems;
+      for (int e = tid; e < nitems; e += PF_WG) {
+        const int meta = L.kmeta[e], q = meta & 0xfff, w = meta >> 12;
+        unsigned long long bits = L.kset[e];
+        const int pr = L.plist[q], i = pr & 255, j = pr >> 8;
+        const float4 pi = L.p[i], pj = L.p[j];
+        const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
+        const float x = sq3(make_float3(ijx, ijy, ijz));
+        const float ix = 1.f / x;
+        const int kij = (i << 8) | j;
+        float cxs = 0.f, fix = 0.f, fiy = 0.f, fiz = 0.f, fjx = 0.f, fjy = 0.f, fjz = 0.f, eu = 0.f;
+        int nt = 0;
+        while (bits) {
+          const int k = 64 * w + __builtin_ctzll(bits);
+          bits &= bits - 1ull;
+          const float4 pk = L.p[k];
+          const float ikx = pi.x - pk.x, iky = pi.y - pk.y, ikz = pi.z - pk.z;
+          const float jkx = pj.x - pk.x, jky = pj.y - pk.y, jkz = pj.z - pk.z;
+          const float y = sq3(make_float3(ikx, iky, ikz)), z = sq3(make_float3(jkx, jky, jkz));
+          const int kik = k < i ? ((k << 8) | i) : ((i << 8) | k);
+          const int kjk = k < j ? ((k << 8) | j) : ((j << 8) | k);
+          if (!((y > x || (y == x && kik > kij)) && (z > x || (z == x && kjk > kij)))) continue;
+          const float prod = (x * y) * z;
+          bool in = prod < a.lo6f;
+          if ((!in && prod < a.hi6f) || fminf(x, fminf(y, z)) < a.small2) {
+            const int oi = __float_as_int(pi.w), oj = __float_as_int(pj.w), ok = __float_as_int(pk.w);
+            const double ex = exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]);
+            const double ey = exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]);
+            const double ez = exact_r2(a.pos, oj, ok, a.box[0], a.box[1], a.box[2]);
+            in = product_ok(ex, ey, ez, a.rc6);
+          }
+          if (!in) continue;
+          // eq. (atm) in squared sides and eq. (forcepairs), as atm_vec
+          const float s = x + y + z;
+          const float A = fmaf(-2.f, x, s), B = fmaf(-2.f, y, s), C = fmaf(-2.f, z, s);
+          const float AB = A * B, AC = A * C, BC = B * C;
+          const float P = AB * C, S = AB + AC + BC;
+          const float xy = x * y, xz = x * z;
+          const float t1 = __builtin_amdgcn_rsqf(xy * z);
+          const float t2 = t1 * t1, t3 = t2 * t1, t5 = t3 * t2;
+          const float u = P * t5;
+          eu += fmaf(0.375f, u, t3);
+          const float G = fmaf(a.k15nu, u, a.k3nu * t3);
+          const float H = a.k075nu * t5;
+          const float Gt2 = G * t2, H2 = H + H, nHS = -H * S;
+          const float cx = fmaf(G, ix, fmaf(H2, BC, nHS));
+          const float cy = fmaf(Gt2, xz, fmaf(H2, AC, nHS));
+          const float cz = fmaf(Gt2, xy, fmaf(H2, AB, nHS));
+          cxs += cx;
+          fix = fmaf(cy, ikx, fix);
+          fiy = fmaf(cy, iky, fiy);
+          fiz = fmaf(cy, ikz, fiz);
+          fjx = fmaf(cz, jkx, fjx);
+          fjy = fmaf(cz, jky, fjy);
+          fjz = fmaf(cz, jkz, fjz);
+          const float fkx = -fmaf(cy, ikx, cz * jkx), fky = -fmaf(cy, iky, cz * jky), fkz = -fmaf(cy, ikz, cz * jkz);
+          far |= !(fmaxf(fabsf(fkx), fmaxf(fabsf(fky), fabsf(fkz))) < PF_FIX_LIMIT);
+          atomicAdd(&L.f[0][k], pf_fix(fkx));
+          atomicAdd(&L.f[1][k], pf_fix(fky));
+          atomicAdd(&L.f[2][k], pf_fix(fkz));
+          ++nt;
+        }
+        if (nt) {
+          const float Fix = fmaf(cxs, ijx, fix), Fiy = fmaf(cxs, ijy, fiy), Fiz = fmaf(cxs, ijz, fiz);
+          const float Fjx = fmaf(-cxs, ijx, fjx), Fjy = fmaf(-cxs, ijy, fjy), Fjz = fmaf(-cxs, ijz, fjz);
+          far |= !(fmaxf(fmaxf(fabsf(Fix), fmaxf(fabsf(Fiy), fabsf(Fiz))),
+                         fmaxf(fabsf(Fjx), fmaxf(fabsf(Fjy), fabsf(Fjz)))) < PF_FIX_LIMIT);
+          far |= !(fabsf(eu) < PF_FIX_LIMIT);
+          atomicAdd(&L.f[0][i], pf_fix(Fix));
+          atomicAdd(&L.f[1][i], pf_fix(Fiy));
+          atomicAdd(&L.f[2][i], pf_fix(Fiz));
+          atomicAdd(&L.f[0][j], pf_fix(Fjx));
+          atomicAdd(&L.f[1][j], pf_fix(Fjy));
+          atomicAdd(&L.f[2][j], pf_fix(Fjz));
+          eacc += pf_fix(eu);
+          ntr += nt;
+        }
+      }
+      __syncthreads();
+      if (tid <= PF_NCLS) L.ccnt[tid] = 0;
+      __syncthreads();
+    }
+  }
+  // 5. forces to the per-molecule accumulators, block partials, or the flag
+  //    that hands the base cell to k_prod_block
+  const unsigned long long far_all = (unsigned long long)far;
+  if (fits) {
+    for (int t = tid; t < n; t += PF_WG) {
+      const int o = __float_as_int(L.p[t].w);
+      for (int d = 0; d < 3; ++d) {
+        const unsigned long long v = L.f[d][t];
+        if (v) atomicAdd(&a.acc[3 * (int64_t)o + d], v);
+      }
+    }
+  }
+  unsigned long long e = eacc, nt = (unsigned long long)ntr, fr = far_all;
+  for (int o = 32; o > 0; o >>= 1) {
+    e += __shfl_xor(e, o);
+    nt += __shfl_xor(nt, o);
+    fr |= __shfl_xor(fr, o);
+  }
+  if (lane == 0) {
+    L.red[wave][0] = e;
+    L.red[wave][1] = nt;
+    L.red[wave][2] = fr;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long se = 0, st = 0, sf = 0;
+    for (int q = 0; q < PF_WG / 64; ++q) {
+      se += L.red[q][0];
+      st += L.red[q][1];
+      sf |= L.red[q][2];
+    }
+    a.pdefer[b] = fits ? 0 : 1;
+    a.dpart[4 * b + 0] = 0.0;
+    a.dpart[4 * b + 1] = 0.0;
+    a.dpart[4 * b + 2] = fits ? 3.0 * (double)(long long)se * (1.0 / FIX_SCALE) : 0.0;
+    a.dpart[4 * b + 3] = 0.0;
+    a.ipart[4 * b + 0] = 0;
+    a.ipart[4 * b + 1] = fits ? st : 0;
+    a.ipart[4 * b + 2] = fits ? sf : 0;
+    a.ipart[4 * b + 3] = 0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, int64_t m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < m) p[i] = 0ull;
@@ -975,6 +1430,11 @@ ProdArgs prod_args(const OneArgs& a, const Grid& g, int variant, int splits, uns
   b.lo2f = (float)(a.rc2 * (1.0 - 1e-4));
   b.hi2f = (float)(a.rc2 * (1.0 + 1e-4));
   b.tpart = nullptr;
+  const double t1 = a.rc2 * (1.0 + 1e-4) / 8.0;
+  b.pf_inv_t1 = (float)(1.0 / t1);
+  b.pf_t1sq = (float)(t1 * t1);
+  b.pf_h6 = (float)(a.rc6 * (1.0 + 1e-3));
+  b.pdefer = nullptr;
   return b;
 }
 
@@ -1085,8 +1545,15 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   const int64_t nb1_64 = one_terms ? g.ncells * groups : 0;
   const int splits = prod_splits(g);
   const int64_t nb2_64 = (blockwise && atm) ? g.ncells * splits : 0;
-  if (nb1_64 + nb2_64 > (int64_t)INT32_MAX) return hipErrorInvalidValue;
-  const unsigned nb1 = (unsigned)nb1_64, nb2 = (unsigned)nb2_64, nb = nb1 + nb2;
+  // the shell-pruned tier takes every base cell first where the cell sets
+  // need no minimum-image wrap; k_prod_block the cells it hands on
+  bool wr_set = false;
+  for (int d = 0; d < 3; ++d) wr_set = wr_set || g.n[d] < (p.variant == ATM3_VARIANT_3C08 ? 4 : 6);
+  const int64_t nbf_64 = (blockwise && atm && !wr_set) ? g.ncells : 0;
+  if (nb1_64 + nb2_64 + nbf_64 > (int64_t)INT32_MAX || 8 * ((g.ncells + 7) / 8) > (int64_t)INT32_MAX)
+    return hipErrorInvalidValue;
+  const unsigned nb1 = (unsigned)nb1_64, nbf = (unsigned)nbf_64, nb2 = (unsigned)nb2_64, nb = nb1 + nbf + nb2;
+  if (nbf && ensure(ctx, B_PDEFER, 4 * (size_t)g.ncells)) return hipErrorOutOfMemory;
   // room for the per-block partials and, afterwards, the candidate partials
   // of launch_variant_counts (so that its ensure does not reallocate)
   const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
@@ -1111,8 +1578,18 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   if (nb2) {
     bool wr = false;
     ProdArgs b = prod_args(a, g, p.variant, splits, acc, &wr);
-    b.dpart = dpart + 4 * (size_t)nb1;
-    b.ipart = ipart + 4 * (size_t)nb1;
+    if (nbf) {
+      b.pdefer = (int32_t*)ctx->buf[B_PDEFER];
+      b.dpart = dpart + 4 * (size_t)nb1;
+      b.ipart = ipart + 4 * (size_t)nb1;
+      const unsigned grid = (unsigned)(8 * ((g.ncells + 7) / 8));
+      if (p.variant == ATM3_VARIANT_3C08)
+        hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C08, 2, 2048, 2048, 2>), dim3(grid), dim3(PF_WG), 0, st, b);
+      else
+        hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C18, 3, 4096, 1536, 1>), dim3(grid), dim3(PF_WG), 0, st, b);
+    }
+    b.dpart = dpart + 4 * (size_t)(nb1 + nbf);
+    b.ipart = ipart + 4 * (size_t)(nb1 + nbf);
     launch_prod<false>(b, p.variant, wr, nb2, st);
   }
   if (blockwise)

@@ -161,3 +161,28 @@ def test_virial_diagonal_against_oracle(torch_cuda, orc, trunc, var, terms):
         assert wa.sum() == pytest.approx(r["w_atm"], rel=1e-5)
     else:
         assert np.all(wa == 0.0)
+
+
+@pytest.mark.parametrize("var,L,n", [("3c08", 13.0, 2000), ("3c18", 15.2, 2900)])
+def test_product_rule_dense_mixes_both_tiers(torch_cuda, orc, var, L, n):
+    """Dense packings (density 0.91 and 0.83, molecules 0.8 sigma apart at
+    least) under the product rule: about 40 % of the 3c08 blocks hold more
+    than the 128 molecules of the shell-pruned tier and about 25 % of the
+    3c18 cell sets more than its 192, so one evaluation mixes that tier with
+    the blocks it hands on to k_prod_block.  Whole-system parity against the
+    O(N^3) oracle."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    box = np.array([L, L, L])
+    pos, _ = workloads.rsa(n, box, dmin=0.8, seed=workloads.SEED_BASE + 730)
+    _say(f"[dense product {var}] n={len(pos)} box={L}")
+    ref = orc.brute(pos, box, rc=RC, nu=NU, truncation="product", variant=var)
+    f, r = atm3.compute_forces(torch.from_numpy(pos).cuda(), box, nu=NU, truncation="product", variant=var)
+    torch.cuda.synchronize()
+    assert r["status"] == 0
+    assert (r["n_pairs"], r["n_triplets"], r["n_candidates"]) == (ref.n_pairs, ref.n_triplets, ref.n_candidates)
+    err = force_err(f.cpu().numpy().astype(np.float64), ref.forces)
+    _say(f"  force err {err:.2e}; triplets {r['n_triplets']}")
+    assert err <= 1e-5
+    for key in ("e_lj", "e_atm", "w_lj", "w_atm"):
+        assert r[key] == pytest.approx(getattr(ref, key), rel=1e-6), key
