@@ -550,6 +550,10 @@ struct ProdArgs {
   // k_prod_fast handed the cell on (k_prod_block skips the others)
   float pf_inv_t1, pf_t1sq, pf_h6;
   int32_t* pdefer;
+  // with pdefer: the LJ pairs the cell set owns (Newton 3, fixed point), as
+  // the one-sided kernel is not run then
+  int32_t lj;
+  double sig2, eps4, eps24;
 };
 
 struct ProdLds {
@@ -561,7 +565,29 @@ struct ProdLds {
   double red[PB_WAVES];
   unsigned long long redi[PB_WAVES][2];
   double tred[PB_WAVES][3];
+  double redl[PB_WAVES][2];
+  unsigned long long redp[PB_WAVES];
 };
+
+// The exact minimum-image difference r_a - r_b of input molecules (as in
+// exact_r2, whose squared length it returns).
+__device__ __forceinline__ double exact_vec(const double* __restrict__ pos, int a, int b, const double* box,
+                                            double& ex, double& ey, double& ez) {
+#pragma clang fp contract(off)
+  double d0 = pos[3 * (int64_t)a + 0] - pos[3 * (int64_t)b + 0];
+  d0 = d0 - box[0] * rint(d0 / box[0]);
+  double d1 = pos[3 * (int64_t)a + 1] - pos[3 * (int64_t)b + 1];
+  d1 = d1 - box[1] * rint(d1 / box[1]);
+  double d2 = pos[3 * (int64_t)a + 2] - pos[3 * (int64_t)b + 2];
+  d2 = d2 - box[2] * rint(d2 / box[2]);
+  ex = d0;
+  ey = d1;
+  ez = d2;
+  double s = d0 * d0;
+  s = s + d1 * d1;
+  s = s + d2 * d2;
+  return s;
+}
 
 // eq. (atm) and eq. (forcepairs) from the three pair vectors r_ij = r_i - r_j,
 // r_ik, r_jk and their squared lengths x, y, z: F_i = c_x r_ij + c_y r_ik,
@@ -639,8 +665,8 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
   }
   __syncthreads();
   const int n = L.base[NCS];
-  double e3 = 0.0, tx = 0.0, ty = 0.0, tz = 0.0;
-  unsigned long long ntrip = 0, rng = 0;
+  double e3 = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, elj = 0.0, wlj = 0.0;
+  unsigned long long ntrip = 0, rng = 0, npair = 0;
   const unsigned long long over = n > PB_CAP ? 1 : 0;
   const bool pair = TENSOR && a.pair;
   if (!over) {
@@ -665,6 +691,40 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
       if (WR) d = wrapf(d, a.boxf, a.invf);
       return d;
     };
+    if (!TENSOR && a.lj) {
+      // the LJ pairs the cell set owns (3c08: corner codes AND to zero;
+      // 3c18: the first molecule in the base cell), a wave per row i, rows
+      // shared by the `splits` blocks of the cell; the oracle's FP64
+      // distance decides, FP64 forces in fixed point
+      const int imax_lj = (VAR == ATM3_VARIANT_3C08) ? n : min(n, L.cnt[0]);
+      for (int i = split * PB_WAVES + w; i < imax_lj; i += a.splits * PB_WAVES) {
+        const float4 pi = L.p[i];
+        const int ci = L.code[i];
+        for (int j = i + 1 + lane; j < n; j += 64) {
+          if (VAR == ATM3_VARIANT_3C08 && (ci & L.code[j]) != 0) continue;
+          const float4 pj = L.p[j];
+          if (!(sq3(dvec(pi, pj)) < a.hi2f)) continue;
+          double ex, ey, ez;
+          if (!(exact_vec(a.pos, __float_as_int(pi.w), __float_as_int(pj.w), a.box, ex, ey, ez) < a.rc2)) continue;
+          const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &elj, &wlj);
+          const double gx = f * ex, gy = f * ey, gz = f * ez;
+          if (!(fabs(gx) + fabs(gy) + fabs(gz) < (double)PB_FIX_LIMIT)) {
+            rng = 1;
+          } else {
+            const unsigned long long vx = (unsigned long long)(long long)rint(gx * FIX_SCALE);
+            const unsigned long long vy = (unsigned long long)(long long)rint(gy * FIX_SCALE);
+            const unsigned long long vz = (unsigned long long)(long long)rint(gz * FIX_SCALE);
+            atomicAdd(&L.f[0][i], vx);
+            atomicAdd(&L.f[1][i], vy);
+            atomicAdd(&L.f[2][i], vz);
+            atomicAdd(&L.f[0][j], 0ull - vx);
+            atomicAdd(&L.f[1][j], 0ull - vy);
+            atomicAdd(&L.f[2][j], 0ull - vz);
+          }
+          ++npair;
+        }
+      }
+    }
     uint32_t* qb = L.q[w];
     int qn = 0;
     auto drain = [&](int cnt) {
@@ -764,6 +824,9 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
     e3 += __shfl_xor(e3, o);
     ntrip += __shfl_xor(ntrip, o);
     rng |= __shfl_xor(rng, o);
+    elj += __shfl_xor(elj, o);
+    wlj += __shfl_xor(wlj, o);
+    npair += __shfl_xor(npair, o);
     if (TENSOR) {
       tx += __shfl_xor(tx, o);
       ty += __shfl_xor(ty, o);
@@ -774,6 +837,9 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
     L.red[w] = e3;
     L.redi[w][0] = ntrip;
     L.redi[w][1] = rng;
+    L.redl[w][0] = elj;
+    L.redl[w][1] = wlj;
+    L.redp[w] = npair;
     if (TENSOR) {
       L.tred[w][0] = tx;
       L.tred[w][1] = ty;
@@ -787,19 +853,22 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
     a.tpart[3 * (int64_t)blockIdx.x + threadIdx.x] = t;
   }
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    unsigned long long t = 0, r = 0;
+    double s = 0.0, sl = 0.0, sw = 0.0;
+    unsigned long long t = 0, r = 0, sp = 0;
     for (int q = 0; q < PB_WAVES; ++q) {
       s += L.red[q];
       t += L.redi[q][0];
       r |= L.redi[q][1];
+      sl += L.redl[q][0];
+      sw += L.redl[q][1];
+      sp += L.redp[q];
     }
     const int64_t blk = blockIdx.x;
-    a.dpart[4 * blk + 0] = 0.0;
-    a.dpart[4 * blk + 1] = 0.0;
+    a.dpart[4 * blk + 0] = a.eps4 * sl;
+    a.dpart[4 * blk + 1] = a.eps24 * sw;
     a.dpart[4 * blk + 2] = s;
     a.dpart[4 * blk + 3] = 0.0;
-    a.ipart[4 * blk + 0] = 0;
+    a.ipart[4 * blk + 0] = sp;
     a.ipart[4 * blk + 1] = t;
     a.ipart[4 * blk + 2] = r;
     a.ipart[4 * blk + 3] = over;
@@ -844,6 +913,7 @@ template <int NW, int PCAP, int KCAP>
 struct ProdFastLds {
   static constexpr int MAXB = 64 * NW;
   float4 p[MAXB];                        // block-frame position, .w = input index
+  float lo[3][MAXB];                     // residuals: coordinate - (double)p
   unsigned long long pl[MAXB][NW][4];    // bit k of plane b: bit b of the shell of (i, k)
   unsigned long long own[8][NW];         // 3c08: k with code & m == 0; 3c18: [0] base cell, [1] all
   unsigned long long f[3][MAXB];         // ATM forces, 2^-32 units
@@ -855,12 +925,18 @@ struct ProdFastLds {
   int32_t ccnt[PF_NCLS + 1], cursor[PF_NCLS + 1];
   int32_t wsum[PF_WG / 64];
   int32_t nrows, nitems, abort;
-  unsigned long long red[PF_WG / 64][3];
+  unsigned long long red[PF_WG / 64][4];
+  double redd[PF_WG / 64][2];
 };
 
 // 2^-32 fixed point by a magic add in FP64 (|v| < 2^19; the caller checks).
 __device__ __forceinline__ unsigned long long pf_fix(float v) {
   const double t = (double)v + 1572864.0;
+  return (unsigned long long)__double_as_longlong(t) - 0x4138000000000000ull;
+}
+
+__device__ __forceinline__ unsigned long long pf_fixd(double v) {
+  const double t = v + 1572864.0;
   return (unsigned long long)__double_as_longlong(t) - 0x4138000000000000ull;
 }
 
@@ -964,7 +1040,8 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
   __syncthreads();
   const int n = L.base[NCS];
   unsigned long long eacc = 0ull;
-  int ntr = 0, far = 0;
+  int ntr = 0, far = 0, npair = 0;
+  double elj = 0.0, wlj = 0.0;
   bool fits = n <= MAXB;
   if (fits) {
     // 1. stage the cell set (block frame: relative to the base cell's centre)
@@ -975,8 +1052,12 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       const uint8_t code = (VAR == ATM3_VARIANT_3C08) ? (uint8_t)q : (uint8_t)(q == 0 ? 0 : 1);
       for (int t = lane; t < m; t += 64) {
         const double4 o = a.sorted[t0 + t];
-        L.p[bb + t] = make_float4((float)(o.x + dx * a.side[0]), (float)(o.y + dy * a.side[1]),
-                                  (float)(o.z + dz * a.side[2]), __int_as_float((int)o.w));
+        const double vx = o.x + dx * a.side[0], vy = o.y + dy * a.side[1], vz = o.z + dz * a.side[2];
+        const float hx = (float)vx, hy = (float)vy, hz = (float)vz;
+        L.p[bb + t] = make_float4(hx, hy, hz, __int_as_float((int)o.w));
+        L.lo[0][bb + t] = (float)(vx - (double)hx);
+        L.lo[1][bb + t] = (float)(vy - (double)hy);
+        L.lo[2][bb + t] = (float)(vz - (double)hz);
         L.code[bb + t] = code;
       }
     }
@@ -1057,8 +1138,35 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         for (int t = 0; t < 5; ++t) mc[t] = ((cmax >> t) & 1) ? ~0ull : 0ull;
         const int ci = L.code[i], cj = L.code[j];
         const int om = (VAR == ATM3_VARIANT_3C08) ? (ci & cj) : ((ci == 0 || cj == 0) ? 1 : 0);
+        // the LJ term of an owned pair within rc (FP32 test, the oracle's
+        // FP64 test in a relative band; FP64 on the coordinates with their
+        // residuals), Newton 3 in fixed point
+        if (a.lj && ((VAR == ATM3_VARIANT_3C08) ? om == 0 : om == 1) && x < a.hi2f) {
+          bool in = x < a.lo2f;
+          if (!in)
+            in = exact_r2(a.pos, __float_as_int(pi.w), __float_as_int(pj.w), a.box[0], a.box[1], a.box[2]) < a.rc2;
+          if (in) {
+            const double ex = ((double)pi.x - (double)pj.x) + ((double)L.lo[0][i] - (double)L.lo[0][j]);
+            const double ey = ((double)pi.y - (double)pj.y) + ((double)L.lo[1][i] - (double)L.lo[1][j]);
+            const double ez = ((double)pi.z - (double)pj.z) + ((double)L.lo[2][i] - (double)L.lo[2][j]);
+            const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &elj, &wlj);
+            const double gx = f * ex, gy = f * ey, gz = f * ez;
+            far |= !(fabs(gx) + fabs(gy) + fabs(gz) < (double)PF_FIX_LIMIT);
+            atomicAdd(&L.f[0][i], pf_fixd(gx));
+            atomicAdd(&L.f[1][i], pf_fixd(gy));
+            atomicAdd(&L.f[2][i], pf_fixd(gz));
+            atomicAdd(&L.f[0][j], pf_fixd(-gx));
+            atomicAdd(&L.f[1][j], pf_fixd(-gy));
+            atomicAdd(&L.f[2][j], pf_fixd(-gz));
+            ++npair;
+          }
+        }
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
+          // words holding no molecule the row may take (rows whose third
+          // molecule must lie in the base cell, or corner 0 of 3c08) are skipped
+          const unsigned long long ow = L.own[om][w];
+          if (ow == 0ull) continue;
           unsigned long long vi[4], vj[4], s[5];
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
@@ -1074,7 +1182,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
             c = (vi[t] & vj[t]) | (c & h);
           }
           s[4] = c;
-          unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & L.own[om][w];
+          unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & ow;
           if ((i >> 6) == w) kw &= ~(1ull << (i & 63));
           if ((j >> 6) == w) kw &= ~(1ull << (j & 63));
           K[rr][w] = kw;
@@ -1219,31 +1327,41 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       }
     }
   }
-  unsigned long long e = eacc, nt = (unsigned long long)ntr, fr = far_all;
+  unsigned long long e = eacc, nt = (unsigned long long)ntr, fr = far_all, np2 = (unsigned long long)npair;
   for (int o = 32; o > 0; o >>= 1) {
     e += __shfl_xor(e, o);
     nt += __shfl_xor(nt, o);
     fr |= __shfl_xor(fr, o);
+    np2 += __shfl_xor(np2, o);
+    elj += __shfl_xor(elj, o);
+    wlj += __shfl_xor(wlj, o);
   }
   if (lane == 0) {
     L.red[wave][0] = e;
     L.red[wave][1] = nt;
     L.red[wave][2] = fr;
+    L.red[wave][3] = np2;
+    L.redd[wave][0] = elj;
+    L.redd[wave][1] = wlj;
   }
   __syncthreads();
   if (tid == 0) {
-    unsigned long long se = 0, st = 0, sf = 0;
+    unsigned long long se = 0, st = 0, sf = 0, sp = 0;
+    double sel = 0.0, swl = 0.0;
     for (int q = 0; q < PF_WG / 64; ++q) {
       se += L.red[q][0];
       st += L.red[q][1];
       sf |= L.red[q][2];
+      sp += L.red[q][3];
+      sel += L.redd[q][0];
+      swl += L.redd[q][1];
     }
     a.pdefer[b] = fits ? 0 : 1;
-    a.dpart[4 * b + 0] = 0.0;
-    a.dpart[4 * b + 1] = 0.0;
+    a.dpart[4 * b + 0] = fits ? a.eps4 * sel : 0.0;
+    a.dpart[4 * b + 1] = fits ? a.eps24 * swl : 0.0;
     a.dpart[4 * b + 2] = fits ? 3.0 * (double)(long long)se * (1.0 / FIX_SCALE) : 0.0;
     a.dpart[4 * b + 3] = 0.0;
-    a.ipart[4 * b + 0] = 0;
+    a.ipart[4 * b + 0] = fits ? sp : 0;
     a.ipart[4 * b + 1] = fits ? st : 0;
     a.ipart[4 * b + 2] = fits ? sf : 0;
     a.ipart[4 * b + 3] = 0;
@@ -1435,6 +1553,10 @@ ProdArgs prod_args(const OneArgs& a, const Grid& g, int variant, int splits, uns
   b.pf_t1sq = (float)(t1 * t1);
   b.pf_h6 = (float)(a.rc6 * (1.0 + 1e-3));
   b.pdefer = nullptr;
+  b.lj = 0;
+  b.sig2 = a.sig2;
+  b.eps4 = a.eps4;
+  b.eps24 = a.eps24;
   return b;
 }
 
@@ -1538,18 +1660,20 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   // both terms; 3c08 and 3c18 run it for LJ only and the block
   // kernel for ATM
   const bool blockwise = p.variant != ATM3_VARIANT_3C01;
-  const int one_terms = blockwise ? (p.terms & ATM3_TERM_LJ) : p.terms;
+  // the shell-pruned tier takes every base cell first where the cell sets
+  // need no minimum-image wrap, with the LJ pairs the sets own; k_prod_block
+  // the cells it hands on
+  bool wr_set = false;
+  for (int d = 0; d < 3; ++d) wr_set = wr_set || g.n[d] < (p.variant == ATM3_VARIANT_3C08 ? 4 : 6);
+  const bool fast = blockwise && atm && !wr_set;
+  const int one_terms = fast ? 0 : (blockwise ? (p.terms & ATM3_TERM_LJ) : p.terms);
   int groups = 1;
   bool wv = false, wj = false;
-  OneArgs a = one_args(ctx, pos, n, g, p, one_terms, forces, &groups, &wv, &wj);
+  OneArgs a = one_args(ctx, pos, n, g, p, one_terms ? one_terms : ATM3_TERM_LJ, forces, &groups, &wv, &wj);
   const int64_t nb1_64 = one_terms ? g.ncells * groups : 0;
   const int splits = prod_splits(g);
   const int64_t nb2_64 = (blockwise && atm) ? g.ncells * splits : 0;
-  // the shell-pruned tier takes every base cell first where the cell sets
-  // need no minimum-image wrap; k_prod_block the cells it hands on
-  bool wr_set = false;
-  for (int d = 0; d < 3; ++d) wr_set = wr_set || g.n[d] < (p.variant == ATM3_VARIANT_3C08 ? 4 : 6);
-  const int64_t nbf_64 = (blockwise && atm && !wr_set) ? g.ncells : 0;
+  const int64_t nbf_64 = fast ? g.ncells : 0;
   if (nb1_64 + nb2_64 + nbf_64 > (int64_t)INT32_MAX || 8 * ((g.ncells + 7) / 8) > (int64_t)INT32_MAX)
     return hipErrorInvalidValue;
   const unsigned nb1 = (unsigned)nb1_64, nbf = (unsigned)nbf_64, nb2 = (unsigned)nb2_64, nb = nb1 + nbf + nb2;
@@ -1580,6 +1704,7 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
     ProdArgs b = prod_args(a, g, p.variant, splits, acc, &wr);
     if (nbf) {
       b.pdefer = (int32_t*)ctx->buf[B_PDEFER];
+      b.lj = lj ? 1 : 0;
       b.dpart = dpart + 4 * (size_t)nb1;
       b.ipart = ipart + 4 * (size_t)nb1;
       const unsigned grid = (unsigned)(8 * ((g.ncells + 7) / 8));
@@ -1593,7 +1718,8 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
     launch_prod<false>(b, p.variant, wr, nb2, st);
   }
   if (blockwise)
-    hipLaunchKernelGGL(k_prod_forces, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st, lj ? (const double*)ljf : nullptr,
+    hipLaunchKernelGGL(k_prod_forces, dim3(blocks_for(3 * n, 256)), dim3(256), 0, st,
+                       (lj && nb1) ? (const double*)ljf : nullptr,
                        (const unsigned long long*)acc, 3 * n, forces);
   e = phase_end(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
