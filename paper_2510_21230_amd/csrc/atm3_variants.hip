@@ -914,7 +914,7 @@ struct ProdFastLds {
   static constexpr int MAXB = 64 * NW;
   float4 p[MAXB];                        // block-frame position, .w = input index
   float lo[3][MAXB];                     // residuals: coordinate - (double)p
-  unsigned long long pl[MAXB][NW][4];    // bit k of plane b: bit b of the shell of (i, k)
+  alignas(16) unsigned long long pl[MAXB][NW][4];  // bit k of plane b: bit b of the shell of (i, k)
   unsigned long long own[8][NW];         // 3c08: k with code & m == 0; 3c18: [0] base cell, [1] all
   unsigned long long f[3][MAXB];         // ATM forces, 2^-32 units
   uint16_t plist[PCAP];                  // rows i | j << 8, i < j
@@ -1074,7 +1074,10 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         s = pf_shell(sq3(make_float3(pi.x - pk.x, pi.y - pk.y, pi.z - pk.z)), a.pf_inv_t1);
       }
       const unsigned long long b0 = __ballot(s & 1), b1 = __ballot(s & 2), b2 = __ballot(s & 4), b3 = __ballot(s & 8);
-      if (lane < 4) L.pl[i][w][lane] = lane == 0 ? b0 : (lane == 1 ? b1 : (lane == 2 ? b2 : b3));
+      if (lane == 0) {
+        *(ulonglong2*)&L.pl[i][w][0] = make_ulonglong2(b0, b1);
+        *(ulonglong2*)&L.pl[i][w][2] = make_ulonglong2(b2, b3);
+      }
     }
     constexpr int NOWN = (VAR == ATM3_VARIANT_3C08) ? 8 : 2;
     for (int task = wave; task < NOWN * NW; task += PF_WG / 64) {
@@ -1383,6 +1386,38 @@ __global__ __launch_bounds__(256) void k_prod_forces(const double* __restrict__ 
   forces[i] = (float)(lj ? lj[i] + f3 : f3);
 }
 
+// First stage of the fixed-order sums: block g adds the partials
+// [g * chunk, (g + 1) * chunk) of dpart / ipart into entry g of dout / iout.
+__global__ __launch_bounds__(256) void k_partials_sum(const double* __restrict__ dpart,
+                                                      const unsigned long long* __restrict__ ipart, int32_t nb,
+                                                      int32_t chunk, double* __restrict__ dout,
+                                                      unsigned long long* __restrict__ iout) {
+  __shared__ double sd[3][256];
+  __shared__ unsigned long long si[4][256];
+  const int tid = threadIdx.x;
+  const int64_t lo = (int64_t)blockIdx.x * chunk, hi = min((int64_t)nb, lo + chunk);
+  double d[3] = {0.0, 0.0, 0.0};
+  unsigned long long c[4] = {0, 0, 0, 0};
+  for (int64_t b = lo + tid; b < hi; b += 256) {
+    for (int k = 0; k < 3; ++k) d[k] += dpart[4 * b + k];
+    for (int k = 0; k < 4; ++k) c[k] += ipart[4 * b + k];
+  }
+  for (int k = 0; k < 3; ++k) sd[k][tid] = d[k];
+  for (int k = 0; k < 4; ++k) si[k][tid] = c[k];
+  __syncthreads();
+  for (int half = 128; half > 0; half >>= 1) {
+    if (tid < half) {
+      for (int k = 0; k < 3; ++k) sd[k][tid] += sd[k][tid + half];
+      for (int k = 0; k < 4; ++k) si[k][tid] += si[k][tid + half];
+    }
+    __syncthreads();
+  }
+  if (tid < 4) {
+    dout[4 * (int64_t)blockIdx.x + tid] = tid < 3 ? sd[tid][0] : 0.0;
+    iout[4 * (int64_t)blockIdx.x + tid] = si[tid][0];
+  }
+}
+
 // Fixed-order sums of the per-block partials into the result.  The ATM
 // energy partials hold 3 u / nu per triplet (once per receiving molecule in
 // the one-sided kernel, three times u once per triplet in the block kernel),
@@ -1680,7 +1715,7 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
   if (nbf && ensure(ctx, B_PDEFER, 4 * (size_t)g.ncells)) return hipErrorOutOfMemory;
   // room for the per-block partials and, afterwards, the candidate partials
   // of launch_variant_counts (so that its ensure does not reallocate)
-  const size_t need = 64 * (size_t)nb + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
+  const size_t need = 64 * (size_t)nb + 64 * 256 + 64, need_c = 8 * (size_t)blocks_for(g.ncells, 256) + 64;
   if (ensure(ctx, B_SRED, need > need_c ? need : need_c)) return hipErrorOutOfMemory;
   double* dpart = (double*)ctx->buf[B_SRED];
   unsigned long long* ipart = (unsigned long long*)(dpart + 4 * (size_t)nb);
@@ -1723,7 +1758,15 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
                        (const unsigned long long*)acc, 3 * n, forces);
   e = phase_end(ctx, ATM3_PHASE_BLOCK);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, st, dpart, ipart, (int32_t)nb, p.nu, g.n[0], g.n[1],
+  // two stages: 256 blocks over the partials, then one over their sums
+  const int32_t chunk = (int32_t)std::max<int64_t>(1, ((int64_t)nb + 255) / 256);
+  const int32_t ng = (int32_t)(((int64_t)nb + chunk - 1) / chunk);
+  double* dsum = (double*)(ipart + 4 * (size_t)nb);
+  unsigned long long* isum = (unsigned long long*)(dsum + 4 * 256);
+  if (ng > 0)
+    hipLaunchKernelGGL(k_partials_sum, dim3(ng), dim3(256), 0, st, (const double*)dpart,
+                       (const unsigned long long*)ipart, (int32_t)nb, chunk, dsum, isum);
+  hipLaunchKernelGGL(k_onesided_final, dim3(1), dim3(256), 0, st, dsum, isum, ng, p.nu, g.n[0], g.n[1],
                      g.n[2], res_dev);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // the candidates of the variant's cell sets, from the cell populations

@@ -186,3 +186,31 @@ def test_product_rule_dense_mixes_both_tiers(torch_cuda, orc, var, L, n):
     assert err <= 1e-5
     for key in ("e_lj", "e_atm", "w_lj", "w_atm"):
         assert r[key] == pytest.approx(getattr(ref, key), rel=1e-6), key
+
+
+@pytest.mark.parametrize("var", ["3c08", "3c18"])
+def test_product_rule_fcc1m_sampled(torch_cuda, orc, var):
+    """The product rule at the benchmark size (fcc1m: N = 10^6, 44^3 cells,
+    the shell-pruned tier with the LJ pairs folded in, as timed): forces of
+    2,000 seeded-random molecules against the per-molecule FP64 oracle, the
+    evaluation reproducible bit for bit, and the LJ pairs, energy and virial
+    equal to the pairwise-cutoff path's."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    pos, box = workloads.make("fcc1m")
+    p = torch.from_numpy(pos).cuda()
+    _say(f"[product fcc1m {var}]")
+    f, r = atm3.compute_forces(p, box, nu=NU, truncation="product", variant=var)
+    f2, r2 = atm3.compute_forces(p, box, nu=NU, truncation="product", variant=var)
+    _, rp = atm3.compute_forces(p, box, nu=NU)
+    torch.cuda.synchronize()
+    assert r["status"] == 0
+    assert torch.equal(f, f2) and r == r2
+    assert r["n_pairs"] == rp["n_pairs"]
+    assert r["e_lj"] == pytest.approx(rp["e_lj"], rel=1e-9)
+    assert r["w_lj"] == pytest.approx(rp["w_lj"], rel=1e-9)
+    sample = np.sort(np.random.default_rng(12).choice(len(pos), 2000, replace=False))
+    ref = orc.molecules(pos, box, rc=RC, nu=NU, truncation="product", variant=var, sample=sample)
+    err = force_err(f.cpu().numpy().astype(np.float64)[sample], ref.forces)
+    _say(f"  force err {err:.2e} over 2000 molecules; triplets {r['n_triplets']}")
+    assert err <= 1e-5
