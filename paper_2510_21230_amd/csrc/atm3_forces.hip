@@ -726,14 +726,20 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
 #pragma unroll
     for (int k = 0; k < WPT; ++k) {
       const int wd = tid + WG * k, ri = wd / NW, jb = 64 * (wd % NW);
-      u64 x = wo[k], y = wn[k];
-      while (x) {
-        L.plist[o++] = (uint16_t)(ri | ((jb + __builtin_ctzll(x)) << 8));
-        x &= x - 1ull;
-      }
-      while (y) {
-        L.plist[p++] = (uint16_t)(ri | ((jb + __builtin_ctzll(y)) << 8));
-        y &= y - 1ull;
+      // bits walked as 32-bit halves (one find-first-set and two operations
+      // per bit instead of their 64-bit sequences)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int base = ri | ((jb + 32 * h) << 8);
+        uint32_t x = (uint32_t)(wo[k] >> (32 * h)), y = (uint32_t)(wn[k] >> (32 * h));
+        while (x) {
+          L.plist[o++] = (uint16_t)(base + (__builtin_ctz(x) << 8));
+          x &= x - 1u;
+        }
+        while (y) {
+          L.plist[p++] = (uint16_t)(base + (__builtin_ctz(y) << 8));
+          y &= y - 1u;
+        }
       }
     }
   }
