@@ -137,8 +137,8 @@ int atm3_bin_cells(atm3_ctx* ctx, const double* pos, int64_t n, const double box
  * the product rule, the 27 cells around one cell hold more than 2048 or
  * one 3c08 / 3c18 cell set more than 512.
  * Returns ATM3_ERANGE if a force term or sum reaches 2^31 in magnitude
- * (pair rule) or an ATM force term reaches 2^18 (product rule with 3c08 /
- * 3c18).  Forces are accumulated exactly in 64-bit fixed point with 2^-32
+ * (pair rule) or an ATM or LJ force term reaches 2^18 (product rule with
+ * 3c08 / 3c18).  Forces are accumulated exactly in 64-bit fixed point with 2^-32
  * resolution and are undefined after either error.  Results are
  * reproducible bit for bit between calls. */
 int atm3_compute_forces(atm3_ctx* ctx, const double* pos, int64_t n, const double box[3],
