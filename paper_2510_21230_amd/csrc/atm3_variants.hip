@@ -922,9 +922,9 @@ struct ProdFastLds {
   uint16_t kmeta[KCAP];                  // row | w << 12
   uint8_t code[MAXB];
   int32_t cnt[16], base[16], cell[16];
-  int32_t ccnt[PF_NCLS + 1], cursor[PF_NCLS + 1];
+  int32_t ccnt[2][PF_NCLS + 1], cursor[PF_NCLS + 1];  // class counts per half of the workgroup
   int32_t wsum[PF_WG / 64];
-  int32_t nrows, nitems, abort;
+  int32_t nrows, nitems, abort, nsub;
   unsigned long long red[PF_WG / 64][4];
   double redd[PF_WG / 64][2];
 };
@@ -1003,6 +1003,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
   constexpr int MAXB = Lds::MAXB;
   constexpr int NCS = (VAR == ATM3_VARIANT_3C08) ? 8 : 14;
   static_assert(PCAP <= 4096 && NW <= 4 && MAXB <= 256, "12-bit rows, 2-bit words, 8-bit molecule indices");
+  static_assert(PF_WG == 256, "two halves of 128 threads (tid >> 7)");
   __shared__ Lds L;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ncells = (int64_t)a.nx * a.ny * a.nz;
@@ -1026,7 +1027,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
     L.cell[tid] = cc;
     L.cnt[tid] = a.start[cc + 1] - a.start[cc];
   }
-  if (tid <= PF_NCLS) L.ccnt[tid] = 0;
+  if (tid < 2 * (PF_NCLS + 1)) L.ccnt[tid / (PF_NCLS + 1)][tid % (PF_NCLS + 1)] = 0;
   if (tid == 0) L.abort = 0;
   __syncthreads();
   if (tid == 0) {
@@ -1119,96 +1120,98 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       }
     }
     __syncthreads();
-    // 4. rounds of PF_WG * RPT rows: kept third molecules, items, ATM
-    for (int r0 = 0; fits && r0 < nrows; r0 += PF_WG * RPT) {
-      unsigned long long K[RPT][NW];
+    // 4. rounds of PF_WG * RPT rows: kept third molecules, items, ATM.
+    //    row_words: the K words of row q (zero past the rows), with the
+    //    row's LJ term when `lj` (once per row)
+    auto row_words = [&](int q, unsigned long long* Kq, bool lj) {
 #pragma unroll
-      for (int rr = 0; rr < RPT; ++rr) {
-        const int q = r0 + rr * PF_WG + tid;
+      for (int w = 0; w < NW; ++w) Kq[w] = 0ull;
+      if (q >= nrows) return;
+      const int pr = L.plist[q], i = pr & 255, j = pr >> 8;
+      const float4 pi = L.p[i], pj = L.p[j];
+      const float x = sq3(make_float3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z));
+      const int ax = pf_shell(x, a.pf_inv_t1);
+      int cmax = 31;
+      if (ax > 0) cmax = min(31, (int)ceilf(2.f * __log2f(a.pf_h6 / (a.pf_t1sq * x)) + 1e-3f) + 1);
+      unsigned long long mx[4], mc[5];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) K[rr][w] = 0ull;
-        if (q >= nrows) continue;
-        const int pr = L.plist[q], i = pr & 255, j = pr >> 8;
-        const float4 pi = L.p[i], pj = L.p[j];
-        const float x = sq3(make_float3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z));
-        const int ax = pf_shell(x, a.pf_inv_t1);
-        int cmax = 31;
-        if (ax > 0) cmax = min(31, (int)ceilf(2.f * __log2f(a.pf_h6 / (a.pf_t1sq * x)) + 1e-3f) + 1);
-        unsigned long long mx[4], mc[5];
+      for (int t = 0; t < 4; ++t) mx[t] = ((ax >> t) & 1) ? ~0ull : 0ull;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) mx[t] = ((ax >> t) & 1) ? ~0ull : 0ull;
-#pragma unroll
-        for (int t = 0; t < 5; ++t) mc[t] = ((cmax >> t) & 1) ? ~0ull : 0ull;
-        const int ci = L.code[i], cj = L.code[j];
-        const int om = (VAR == ATM3_VARIANT_3C08) ? (ci & cj) : ((ci == 0 || cj == 0) ? 1 : 0);
-        // the LJ term of an owned pair within rc (FP32 test, the oracle's
-        // FP64 test in a relative band; FP64 on the coordinates with their
-        // residuals), Newton 3 in fixed point
-        if (a.lj && ((VAR == ATM3_VARIANT_3C08) ? om == 0 : om == 1) && x < a.hi2f) {
-          bool in = x < a.lo2f;
-          if (!in)
-            in = exact_r2(a.pos, __float_as_int(pi.w), __float_as_int(pj.w), a.box[0], a.box[1], a.box[2]) < a.rc2;
-          if (in) {
-            const double ex = ((double)pi.x - (double)pj.x) + ((double)L.lo[0][i] - (double)L.lo[0][j]);
-            const double ey = ((double)pi.y - (double)pj.y) + ((double)L.lo[1][i] - (double)L.lo[1][j]);
-            const double ez = ((double)pi.z - (double)pj.z) + ((double)L.lo[2][i] - (double)L.lo[2][j]);
-            const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &elj, &wlj);
-            const double gx = f * ex, gy = f * ey, gz = f * ez;
-            far |= !(fabs(gx) + fabs(gy) + fabs(gz) < (double)PF_FIX_LIMIT);
-            atomicAdd(&L.f[0][i], pf_fixd(gx));
-            atomicAdd(&L.f[1][i], pf_fixd(gy));
-            atomicAdd(&L.f[2][i], pf_fixd(gz));
-            atomicAdd(&L.f[0][j], pf_fixd(-gx));
-            atomicAdd(&L.f[1][j], pf_fixd(-gy));
-            atomicAdd(&L.f[2][j], pf_fixd(-gz));
-            ++npair;
-          }
-        }
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          // words holding no molecule the row may take (rows whose third
-          // molecule must lie in the base cell, or corner 0 of 3c08) are skipped
-          const unsigned long long ow = L.own[om][w];
-          if (ow == 0ull) continue;
-          unsigned long long vi[4], vj[4], s[5];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            vi[t] = L.pl[i][w][t];
-            vj[t] = L.pl[j][w][t];
-          }
-          // s = shell(i, k) + shell(j, k), five planes
-          unsigned long long c = 0ull;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const unsigned long long h = vi[t] ^ vj[t];
-            s[t] = h ^ c;
-            c = (vi[t] & vj[t]) | (c & h);
-          }
-          s[4] = c;
-          unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & ow;
-          if ((i >> 6) == w) kw &= ~(1ull << (i & 63));
-          if ((j >> 6) == w) kw &= ~(1ull << (j & 63));
-          K[rr][w] = kw;
-          const int p = __popcll(kw);
-          if (p >= PF_NCLS) atomicAdd(&L.ccnt[PF_NCLS], p / PF_NCLS);
-          if (p % PF_NCLS) atomicAdd(&L.ccnt[p % PF_NCLS], 1);
+      for (int t = 0; t < 5; ++t) mc[t] = ((cmax >> t) & 1) ? ~0ull : 0ull;
+      const int ci = L.code[i], cj = L.code[j];
+      const int om = (VAR == ATM3_VARIANT_3C08) ? (ci & cj) : ((ci == 0 || cj == 0) ? 1 : 0);
+      // the LJ term of an owned pair within rc (FP32 test, the oracle's
+      // FP64 test in a relative band; FP64 on the coordinates with their
+      // residuals), Newton 3 in fixed point
+      if (lj && a.lj && ((VAR == ATM3_VARIANT_3C08) ? om == 0 : om == 1) && x < a.hi2f) {
+        bool in = x < a.lo2f;
+        if (!in)
+          in = exact_r2(a.pos, __float_as_int(pi.w), __float_as_int(pj.w), a.box[0], a.box[1], a.box[2]) < a.rc2;
+        if (in) {
+          const double ex = ((double)pi.x - (double)pj.x) + ((double)L.lo[0][i] - (double)L.lo[0][j]);
+          const double ey = ((double)pi.y - (double)pj.y) + ((double)L.lo[1][i] - (double)L.lo[1][j]);
+          const double ez = ((double)pi.z - (double)pj.z) + ((double)L.lo[2][i] - (double)L.lo[2][j]);
+          const double f = lj_pair(ex, ey, ez, a.sig2, a.eps24, &elj, &wlj);
+          const double gx = f * ex, gy = f * ey, gz = f * ez;
+          far |= !(fabs(gx) + fabs(gy) + fabs(gz) < (double)PF_FIX_LIMIT);
+          atomicAdd(&L.f[0][i], pf_fixd(gx));
+          atomicAdd(&L.f[1][i], pf_fixd(gy));
+          atomicAdd(&L.f[2][i], pf_fixd(gz));
+          atomicAdd(&L.f[0][j], pf_fixd(-gx));
+          atomicAdd(&L.f[1][j], pf_fixd(-gy));
+          atomicAdd(&L.f[2][j], pf_fixd(-gz));
+          ++npair;
         }
       }
-      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        // words holding no molecule the row may take (rows whose third
+        // molecule must lie in the base cell, or corner 0 of 3c08) are skipped
+        const unsigned long long ow = L.own[om][w];
+        if (ow == 0ull) continue;
+        unsigned long long vi[4], vj[4], s[5];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          vi[t] = L.pl[i][w][t];
+          vj[t] = L.pl[j][w][t];
+        }
+        // s = shell(i, k) + shell(j, k), five planes
+        unsigned long long c = 0ull;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const unsigned long long h = vi[t] ^ vj[t];
+          s[t] = h ^ c;
+          c = (vi[t] & vj[t]) | (c & h);
+        }
+        s[4] = c;
+        unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & ow;
+        if ((i >> 6) == w) kw &= ~(1ull << (i & 63));
+        if ((j >> 6) == w) kw &= ~(1ull << (j & 63));
+        Kq[w] = kw;
+      }
+    };
+    // items of one row per size class, in the counters of this thread's half
+    auto count_items = [&](const unsigned long long* Kq) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int p = __popcll(Kq[w]);
+        if (p >= PF_NCLS) atomicAdd(&L.ccnt[tid >> 7][PF_NCLS], p / PF_NCLS);
+        if (p % PF_NCLS) atomicAdd(&L.ccnt[tid >> 7][p % PF_NCLS], 1);
+      }
+    };
+    // class cursors, largest items first: both halves (sub < 0) or one
+    auto set_cursors = [&](int sub) {
       if (tid == 0) {
         int run = 0;
-        for (int c = PF_NCLS; c >= 1; --c) {  // largest items first
+        for (int c = PF_NCLS; c >= 1; --c) {
           L.cursor[c] = run;
-          run += L.ccnt[c];
+          run += sub < 0 ? L.ccnt[0][c] + L.ccnt[1][c] : L.ccnt[sub][c];
         }
         L.nitems = run;
-        if (run > KCAP) L.abort = 1;
       }
-      __syncthreads();
-      if (L.abort) {
-        fits = false;
-        break;
-      }
+    };
+    // this thread's items: runs of PF_NCLS set bits, lowest first, then the rest
+    auto place_items = [&](int r0, unsigned long long (&K)[RPT][NW]) {
 #pragma unroll
       for (int rr = 0; rr < RPT; ++rr) {
         const int q = r0 + rr * PF_WG + tid;
@@ -1218,7 +1221,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           while (bits) {
             unsigned long long run = bits;
             int c = __popcll(bits);
-            if (c > PF_NCLS) {  // the lowest PF_NCLS set bits
+            if (c > PF_NCLS) {
               run = 0ull;
               unsigned long long t = bits;
               for (int u = 0; u < PF_NCLS; ++u) {
@@ -1234,7 +1237,9 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           }
         }
       }
-      __syncthreads();
+    };
+    // a thread per item: designation, product test, ATM on all three molecules
+    auto atm_pass = [&]() {
       const int nitems = L.nitems;
       for (int e = tid; e < nitems; e += PF_WG) {
         const int meta = L.kmeta[e], q = meta & 0xfff, w = meta >> 12;
@@ -1313,8 +1318,53 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           ntr += nt;
         }
       }
+    };
+    for (int r0 = 0; fits && r0 < nrows; r0 += PF_WG * RPT) {
+      unsigned long long K[RPT][NW];
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr) {
+        row_words(r0 + rr * PF_WG + tid, K[rr], true);
+        count_items(K[rr]);
+      }
       __syncthreads();
-      if (tid <= PF_NCLS) L.ccnt[tid] = 0;
+      // the round's items: in one pass if they fit KCAP, else the two halves
+      // of the workgroup's rows one after the other, the second half forming
+      // its K words again (the block is handed on only if one half alone
+      // overflows)
+      if (tid == 0) {
+        int t0 = 0, t1 = 0;
+        for (int c = 1; c <= PF_NCLS; ++c) {
+          t0 += L.ccnt[0][c];
+          t1 += L.ccnt[1][c];
+        }
+        L.nsub = (t0 + t1 <= KCAP) ? 1 : 2;
+        if (t0 > KCAP || t1 > KCAP) L.abort = 1;
+      }
+      __syncthreads();
+      if (L.abort) {
+        fits = false;
+        break;
+      }
+      const int nsub = L.nsub;
+      set_cursors(nsub == 1 ? -1 : 0);
+      __syncthreads();
+      if (nsub == 1 || (tid >> 7) == 0) place_items(r0, K);
+      __syncthreads();
+      atm_pass();
+      __syncthreads();
+      if (nsub == 2) {
+        set_cursors(1);
+        __syncthreads();
+        if ((tid >> 7) == 1) {
+#pragma unroll
+          for (int rr = 0; rr < RPT; ++rr) row_words(r0 + rr * PF_WG + tid, K[rr], false);
+          place_items(r0, K);
+        }
+        __syncthreads();
+        atm_pass();
+        __syncthreads();
+      }
+      if (tid < 2 * (PF_NCLS + 1)) L.ccnt[tid / (PF_NCLS + 1)][tid % (PF_NCLS + 1)] = 0;
       __syncthreads();
     }
   }
@@ -1743,7 +1793,12 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
       b.dpart = dpart + 4 * (size_t)nb1;
       b.ipart = ipart + 4 * (size_t)nb1;
       const unsigned grid = (unsigned)(8 * ((g.ncells + 7) / 8));
-      if (p.variant == ATM3_VARIANT_3C08)
+      // a grid whose mean 3c08 block holds more than 112 molecules (cutoffs
+      // from about 2.8 at density 0.75) would hand on most of its blocks:
+      // three mask words (192 molecules) and rounds of 256 rows instead
+      if (p.variant == ATM3_VARIANT_3C08 && 8 * n > 112 * g.ncells)
+        hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C08, 3, 4096, 1536, 1>), dim3(grid), dim3(PF_WG), 0, st, b);
+      else if (p.variant == ATM3_VARIANT_3C08)
         hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C08, 2, 2048, 2048, 2>), dim3(grid), dim3(PF_WG), 0, st, b);
       else
         hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C18, 3, 4096, 1536, 1>), dim3(grid), dim3(PF_WG), 0, st, b);

@@ -214,3 +214,37 @@ def test_product_rule_fcc1m_sampled(torch_cuda, orc, var):
     err = force_err(f.cpu().numpy().astype(np.float64)[sample], ref.forces)
     _say(f"  force err {err:.2e} over 2000 molecules; triplets {r['n_triplets']}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["fuzz", "fcc32k"])
+def test_product_rule_cutoff_3_takes_the_three_word_tier(torch_cuda, orc, case):
+    """The product rule (3c08) at rc = 3.0 and density 0.65-0.75: a 2x2x2
+    block holds about 170 molecules, beyond the 128 of the two-word
+    shell-pruned tier, so its three-word version (192 molecules) runs over
+    every base cell and hands on the larger blocks.  The fuzz case against
+    the O(N^3) oracle (whole system), fcc32k on 1,000 sampled molecules
+    against the per-molecule oracle."""
+    torch = torch_cuda
+    import paper_2510_21230_amd as atm3
+    rc = 3.0
+    if case == "fuzz":
+        pos, box = workloads.rsa(1400, [13.0, 13.0, 13.0], dmin=0.85, seed=workloads.SEED_BASE + 45)
+    else:
+        pos, box = workloads.make("fcc32k")
+    _say(f"[product rc 3] {case} n={len(pos)}")
+    f, r = atm3.compute_forces(torch.from_numpy(pos).cuda(), box, rc=rc, nu=NU, truncation="product")
+    torch.cuda.synchronize()
+    assert r["status"] == 0
+    fg = f.cpu().numpy().astype(np.float64)
+    if case == "fuzz":
+        ref = orc.brute(pos, box, rc=rc, nu=NU, truncation="product")
+        assert (r["n_pairs"], r["n_triplets"], r["n_candidates"]) == (ref.n_pairs, ref.n_triplets, ref.n_candidates)
+        err = force_err(fg, ref.forces)
+        for key in ("e_lj", "e_atm", "w_lj", "w_atm"):
+            assert r[key] == pytest.approx(getattr(ref, key), rel=1e-6), key
+    else:
+        sample = np.sort(np.random.default_rng(13).choice(len(pos), 1000, replace=False))
+        ref = orc.molecules(pos, box, rc=rc, nu=NU, truncation="product", sample=sample)
+        err = force_err(fg[sample], ref.forces)
+    _say(f"  force err {err:.2e}; triplets {r['n_triplets']}")
+    assert err <= 1e-5
