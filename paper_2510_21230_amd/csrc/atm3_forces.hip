@@ -436,47 +436,47 @@ __global__ __launch_bounds__(256) void k_fmask(FmArgs a) {
     sp[m] = make_float4((float)(v.x + ox), (float)(v.y + oy), (float)(v.z + oz), 0.f);
   }
   __syncthreads();
-  // lanes = (own molecule, forward cell) pairs
+  // lanes = (own molecule, forward row) pairs: staged row r holds, for
+  // (dy, dz) = (0,0), (1,0), (-1,1), (0,1), (1,1), the cells at dx = 0, 1
+  // (row 0) or dx = -1, 0, 1; they are contiguous in the staging, and one
+  // lane builds their 2-3 words (forward index k = 0, 1 in row 0, else
+  // 2 + 3 (r - 1) + dx + 1)
   const int own0 = cst[1], nmol = cst[1 + nown] - own0;
-  for (int L = tid; L < 14 * nmol; L += 256) {
-    const int ai = L / 14, k = L - 14 * ai;
+  // consecutive lanes take consecutive molecules of one row: the lanes of
+  // one own cell read the same candidates at the same time (LDS broadcast)
+  for (int task = tid; task < FM_ROWS * nmol; task += 256) {
+    const int r = task / nmol, ai = task - nmol * r;
     const int am = own0 + ai;  // staged index of the molecule
     int ca = 1;
     while (cst[ca + 1] <= am) ++ca;  // its staged cell (row 0)
     if (cst[ca + 1] - cst[ca] > 32) continue;
-    int dx, dy, dz;
-    if (k == 0) {
-      dx = dy = dz = 0;
-    } else if (k == 1) {
-      dx = 1; dy = 0; dz = 0;
-    } else if (k < 5) {
-      dx = k - 3; dy = 1; dz = 0;
-    } else {
-      dx = (k - 5) % 3 - 1; dy = (k - 5) / 3 - 1; dz = 1;
-    }
-    const int rb = (dz == 0) ? dy : 3 + dy;  // staged row of (dy, dz)
-    const int cb = rb * FM_W + ca + dx;
-    const int b0 = cst[cb], pop = cst[cb + 1] - b0;
-    if (pop > 32) continue;
     const float4 pa = sp[am];
-    const int t0 = (k == 0) ? am - cst[ca] + 1 : 0;
-    uint32_t word = 0u, maybe = 0u;  // inside; inside the guard band
-    for (int t = t0; t < pop; ++t) {
-      const float4 pb = sp[b0 + t];
-      const float ex = pa.x - pb.x, ey = pa.y - pb.y, ez = pa.z - pb.z;
-      const float r2 = ex * ex + ey * ey + ez * ez;
-      word |= (r2 < a.lo2 ? 1u : 0u) << t;
-      maybe |= (r2 < a.hi2 ? 1u : 0u) << t;
+    const int slot_a = cgs[ca] + (am - cst[ca]);
+    const int dx0 = (r == 0) ? 0 : -1;
+    for (int dx = dx0; dx <= 1; ++dx) {
+      const int k = (r == 0) ? dx : 2 + 3 * (r - 1) + dx + 1;
+      const int cb = r * FM_W + ca + dx;
+      const int b0 = cst[cb], pop = cst[cb + 1] - b0;
+      if (pop > 32) continue;
+      const int t0 = (k == 0) ? am - cst[ca] + 1 : 0;
+      uint32_t word = 0u, maybe = 0u;  // inside; inside the guard band
+      for (int t = t0; t < pop; ++t) {
+        const float4 pb = sp[b0 + t];
+        const float ex = pa.x - pb.x, ey = pa.y - pb.y, ez = pa.z - pb.z;
+        const float r2 = ex * ex + ey * ey + ez * ez;
+        word |= (r2 < a.lo2 ? 1u : 0u) << t;
+        maybe |= (r2 < a.hi2 ? 1u : 0u) << t;
+      }
+      maybe &= ~word;
+      while (maybe) {  // the exact decision (oracle expression) inside the band
+        const int t = __builtin_ctz(maybe);
+        maybe &= maybe - 1u;
+        const int ia = (int)a.sorted[slot_a].w;
+        const int ib = (int)a.sorted[cgs[cb] + t].w;
+        if (exact_r2(a.pos, ia, ib, a.box[0], a.box[1], a.box[2]) < a.rc2) word |= 1u << t;
+      }
+      a.fmask[(size_t)slot_a * 14 + k] = word;
     }
-    maybe &= ~word;
-    while (maybe) {  // the exact decision (oracle expression) inside the band
-      const int t = __builtin_ctz(maybe);
-      maybe &= maybe - 1u;
-      const int ia = (int)a.sorted[cgs[ca] + (am - cst[ca])].w;
-      const int ib = (int)a.sorted[cgs[cb] + t].w;
-      if (exact_r2(a.pos, ia, ib, a.box[0], a.box[1], a.box[2]) < a.rc2) word |= 1u << t;
-    }
-    a.fmask[(size_t)(cgs[ca] + (am - cst[ca])) * 14 + k] = word;
   }
 }
 
