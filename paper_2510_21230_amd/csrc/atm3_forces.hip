@@ -620,8 +620,6 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
   if (tid < 16) L.cfull[tid] = 0;
   const bool use_fm = (L.h.okc[0] & L.h.okc[1] & L.h.okc[2] & L.h.okc[3] & L.h.okc[4] & L.h.okc[5] &
                        L.h.okc[6] & L.h.okc[7]) != 0;
-  if (use_fm)
-    for (int q = tid; q < MAXB * NW; q += WG) L.mask[q] = 0ull;
   __syncthreads();
   block_allow<NW>(n, L.scode, L.allow);
   for (int item = wave; item < 4 * NW; item += NWAVE) {  // ucol[c][w], c < 4
@@ -637,17 +635,25 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
   //    corners o' >= o: their offsets o' - o are forward offsets, and corner
   //    o' occupies staged positions cbase[o'] ...
   if (use_fm) {
-    // one task per (row i, corner o2 >= corner of i): its word lands at
-    // bits cbase[o2] ... of row i (LDS OR into the zeroed rows)
-    for (int q = tid; q < 8 * n; q += WG) {
-      const int i = q >> 3, o2 = q & 7, o = L.scode[i];
-      if (o2 < o) continue;
-      const int dx = (o2 & 1) - (o & 1), dy = ((o2 >> 1) & 1) - ((o >> 1) & 1), dz = (o2 >> 2) - (o >> 2);
-      const u64 wd = a.fmask[(size_t)(L.h.cstart[o] + (i - L.h.cbase[o])) * 14 + fwd_index(dx, dy, dz)];
-      if (!wd) continue;
-      const int cb = L.h.cbase[o2], wq = cb >> 6, sh = cb & 63;
-      atomicOr(&L.mask[i * NW + wq], wd << sh);
-      if (sh > 32 && wq + 1 < NW) atomicOr(&L.mask[i * NW + wq + 1], wd >> (64 - sh));
+    // one thread per mask word (row i, word w): the words of the corners
+    // o2 >= corner of i whose staged range meets word w, shifted into
+    // place and ORed in registers, then one store (rows past n are zero)
+    for (int q = tid; q < MAXB * NW; q += WG) {
+      const int i = q / NW, w = q - (q / NW) * NW;
+      u64 acc = 0ull;
+      if (i < n) {
+        const int o = L.scode[i];
+        const size_t rowbase = (size_t)(L.h.cstart[o] + (i - L.h.cbase[o])) * 14;
+#pragma unroll
+        for (int o2 = 0; o2 < 8; ++o2) {
+          const int sh = L.h.cbase[o2] - 64 * w;  // bit of the corner's first molecule in word w
+          if (o2 < o || sh >= 64 || L.h.cbase[o2 + 1] - 64 * w <= 0 || L.h.cbase[o2 + 1] == L.h.cbase[o2]) continue;
+          const int dx = (o2 & 1) - (o & 1), dy = ((o2 >> 1) & 1) - ((o >> 1) & 1), dz = (o2 >> 2) - (o >> 2);
+          const u64 wd = a.fmask[rowbase + fwd_index(dx, dy, dz)];
+          acc |= sh >= 0 ? (wd << sh) : (wd >> (-sh));
+        }
+      }
+      L.mask[q] = acc;
     }
   } else {
     //  ... else one wave per row (rows wave, wave + 4, ...).  Lane l holds
