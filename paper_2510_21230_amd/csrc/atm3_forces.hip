@@ -826,17 +826,20 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
     if (myfull) atomicAdd(&L.cfull[lane & 15], myfull);
     __syncthreads();
     for (int v = 0; v < NWAVE; ++v) ntr += L.cnt2[v];
-    int ne = 0;
-    for (int c = NCLS; c >= 1; --c) {
-      int cnt = L.ccnt[c];
-      if (c == NCLS)
+    if (wave == 0) {
+      // lane l holds class NCLS - l (largest first); a scan gives the
+      // cursors, and the total goes to ccnt[0] (no item has 0 molecules)
+      int cnt = 0;
+      if (lane < NCLS) cnt = L.ccnt[NCLS - lane];
+      if (lane == 0)
         for (int s = 0; s < 16; ++s) cnt += L.cfull[s];
-      if (tid == c) L.cursor[c] = ne;
-      ne += cnt;
+      const int incl = wave_incl_scan(cnt);
+      if (lane < NCLS) L.cursor[NCLS - lane] = incl - cnt;
+      if (lane == NCLS - 1) L.ccnt[0] = incl;
     }
-    const int nne = L.nne;
-    if (ne > KCAP || nne > KCAP) return false;  // uniform: block totals
     __syncthreads();
+    const int ne = L.ccnt[0], nne = L.nne;
+    if (ne > KCAP || nne > KCAP) return false;  // uniform: block totals
 
     // 4b. items: the non-empty K words (lanes = entries, entry 37 tid mod WG
     //     + WG r, so that neighbouring lanes hold pairs of different rows,
