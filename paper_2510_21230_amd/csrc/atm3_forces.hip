@@ -197,22 +197,25 @@ struct BlockHead {
 __device__ int block_cells(const ForceArgs& a, int b, BlockHead& H) {
   const int tid = threadIdx.x;
   const int bx = b % a.nx, by = (b / a.nx) % a.ny, bz = b / (a.nx * a.ny);
-  if (tid < 8) {
-    int cx = bx + (tid & 1), cy = by + ((tid >> 1) & 1), cz = bz + (tid >> 2);
-    if (cx >= a.nx) cx -= a.nx;
-    if (cy >= a.ny) cy -= a.ny;
-    if (cz >= a.nz) cz -= a.nz;
-    const int c = (cz * a.ny + cy) * a.nx + cx;
-    const int s0 = a.start[c];
-    H.cstart[tid] = s0;
-    H.cbase[tid + 1] = a.start[c + 1] - s0;
-    H.okc[tid] = a.fm_ok ? a.fm_ok[c] : 0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    H.cbase[0] = 0;
-    for (int o = 0; o < 8; ++o) H.cbase[o + 1] += H.cbase[o];
-    H.bad = 0;
+  if (tid < 64) {  // wave 0: lane o < 8 takes corner o, a scan gives the offsets
+    int cnt = 0;
+    if (tid < 8) {
+      int cx = bx + (tid & 1), cy = by + ((tid >> 1) & 1), cz = bz + (tid >> 2);
+      if (cx >= a.nx) cx -= a.nx;
+      if (cy >= a.ny) cy -= a.ny;
+      if (cz >= a.nz) cz -= a.nz;
+      const int c = (cz * a.ny + cy) * a.nx + cx;
+      const int s0 = a.start[c];
+      H.cstart[tid] = s0;
+      cnt = a.start[c + 1] - s0;
+      H.okc[tid] = a.fm_ok ? a.fm_ok[c] : 0;
+    }
+    const int incl = wave_incl_scan(cnt);
+    if (tid < 8) H.cbase[tid + 1] = incl;
+    if (tid == 0) {
+      H.cbase[0] = 0;
+      H.bad = 0;
+    }
   }
   __syncthreads();
   return H.cbase[8];
@@ -230,9 +233,15 @@ __device__ __forceinline__ int slot_of(const BlockHead& H, const uint8_t* scode,
 // that hi + lo carries the FP64 coordinate to about 48 bits.
 __device__ void block_stage(const ForceArgs& a, const BlockHead& H, int n, double4* dp, float4* sp, float2* slo,
                             u64* ax, u64* ay, u64* az, uint8_t* scode, int32_t* sorig, int32_t* sslot) {
+  // corner boundaries read once (independent broadcast loads, no chain of
+  // dependent reads per molecule)
+  int cb[8];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) cb[k] = H.cbase[k];
   for (int t = threadIdx.x; t < n; t += WG) {
     int o = 0;
-    while (o < 7 && H.cbase[o + 1] <= t) ++o;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) o += (cb[k] <= t) ? 1 : 0;
     const int s = H.cstart[o] + (t - H.cbase[o]);
     const double4 v = a.sorted[s];
     const double px = v.x + ((o & 1) ? a.half[0] : -a.half[0]);
