@@ -568,7 +568,8 @@ struct LdsTier {
 // c_z r_jk are added to the pair's accumulators, and F_k = -(c_y r_ik +
 // c_z r_jk) (eq. newton3rdlaw) is returned.  x = |r_ij|^2 and ix = 1/x are
 // the pair's.  Adds the energy term without nu to *eu and raises *mx to
-// max |F_k|.
+// max(|c_y|, |c_z|): every side of a triplet the fast path takes is within
+// rc, so |F_k| <= (|c_y| + |c_z|) rc <= 2 rc max(|c_y|, |c_z|) per component.
 struct PairAcc {
   float cx, fix, fiy, fiz, fjx, fjy, fjz, eu, mx;
 };
@@ -607,7 +608,7 @@ __device__ __forceinline__ void atm_third(const float4 pi, const float4 pj, cons
   fkx = -fmaf(cy, ikx, cz * jkx);
   fky = -fmaf(cy, iky, cz * jky);
   fkz = -fmaf(cy, ikz, cz * jkz);
-  q.mx = fmaxf(q.mx, fmaxf(fabsf(fkx), fmaxf(fabsf(fky), fabsf(fkz))));
+  q.mx = fmaxf(q.mx, fmaxf(fabsf(cy), fabsf(cz)));
 }
 
 template <int NW, int PCAP, int KCAP>
@@ -884,43 +885,45 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
     //    converted with to_fix_m; a value beyond its range sends the block to
     //    the general path.
     u64 eacc = 0ull;
-    float tmx = 0.f;  // max |F_k|, and sums of the item totals (NaN-propagating)
+    float tmx = 0.f;  // max of the item totals (NaN-propagating)
+    float cmx = 0.f;  // max |c_y|, |c_z|: |F_k| stays below 2 rc cmx
     for (int p = tid; p < ne; p += WG) {
       const int v = L.kmeta[p];
       const int e = L.plist[v & 8191];
       const int ci = e & 255, cj = e >> 8;
-      const int base = 64 * (v >> 13);
-      const float4* spk = L.sp + base;
-      u64* axk = L.ax + base;
-      u64* ayk = L.ay + base;
-      u64* azk = L.az + base;
       // items of pairs with an odd j walk K from the top: pairs of one row
       // have overlapping K, and lanes holding them would otherwise hit the
       // same F_k address in the same instruction.  The direction is a
       // property of the item, not of the lane it lands on, so that every
-      // item's FP32 sums are the same from run to run
-      const int flip = (cj & 1) ? 63 : 0;
+      // item's FP32 sums are the same from run to run.  Bit t of the walked
+      // word is molecule 64 w + t (upward) or 64 w + 63 - t: its byte
+      // offset in sp is o16 + s16 t, half of it in ax
+      const bool up = (cj & 1) == 0;
+      const int o16 = 16 * (64 * (v >> 13) + (up ? 0 : 63)), s16 = up ? 16 : -16;
       u64 K = L.kset[p];
-      if (flip) K = __builtin_bitreverse64(K);
+      if (!up) K = __builtin_bitreverse64(K);
       const float4 pi = L.sp[ci], pj = L.sp[cj];
       const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
       const float x = ijx * ijx + ijy * ijy + ijz * ijz;
       const float ix = __builtin_amdgcn_rcpf(x);
-      PairAcc q = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, tmx};
-      while (K) {
-        const int k = __builtin_ctzll(K) ^ flip;
+      PairAcc q = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, cmx};
+      do {  // an item is a non-empty run of K
+        const int t = __builtin_ctzll(K);
         K &= K - 1ull;
+        const int a16 = o16 + __mul24(t, s16), a8 = a16 >> 1;
+        const float4 pk = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(L.sp) + a16);
         float fkx, fky, fkz;
-        atm_third(pi, pj, spk[k], x, ix, a.k3nu, a.k15nu, a.k075nu, q, fkx, fky, fkz);
-        atomicAdd(&axk[k], to_fix_m(fkx));
-        atomicAdd(&ayk[k], to_fix_m(fky));
-        atomicAdd(&azk[k], to_fix_m(fkz));
-      }
+        atm_third(pi, pj, pk, x, ix, a.k3nu, a.k15nu, a.k075nu, q, fkx, fky, fkz);
+        atomicAdd(reinterpret_cast<u64*>(reinterpret_cast<char*>(L.ax) + a8), to_fix_m(fkx));
+        atomicAdd(reinterpret_cast<u64*>(reinterpret_cast<char*>(L.ay) + a8), to_fix_m(fky));
+        atomicAdd(reinterpret_cast<u64*>(reinterpret_cast<char*>(L.az) + a8), to_fix_m(fkz));
+      } while (K);
+      cmx = q.mx;
       const float fix = fmaf(q.cx, ijx, q.fix), fiy = fmaf(q.cx, ijy, q.fiy), fiz = fmaf(q.cx, ijz, q.fiz);
       const float fjx = fmaf(-q.cx, ijx, q.fjx), fjy = fmaf(-q.cx, ijy, q.fjy), fjz = fmaf(-q.cx, ijz, q.fjz);
-      // a NaN or infinite F_k makes F_i or F_j NaN or infinite as well
+      // a NaN or infinite c_y or c_z makes F_i or F_j NaN or infinite as well
       const float tot = fabsf(fix) + fabsf(fiy) + fabsf(fiz) + fabsf(fjx) + fabsf(fjy) + fabsf(fjz) + fabsf(q.eu);
-      tmx = fmaxf(q.mx, tot == tot ? tot : INFINITY);
+      tmx = fmaxf(tmx, tot == tot ? tot : INFINITY);
       atomicAdd(&L.ax[ci], to_fix_m(fix));
       atomicAdd(&L.ay[ci], to_fix_m(fiy));
       atomicAdd(&L.az[ci], to_fix_m(fiz));
@@ -929,6 +932,8 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
       atomicAdd(&L.az[cj], to_fix_m(fjz));
       eacc += to_fix_m(q.eu);
     }
+    // sides within sqrt(hi2) (the FP32 guard above rc), with 2.5% margin
+    far |= !(cmx * (2.05f * sqrtf(a.hi2)) < FAST_LIMIT);
     far |= !(tmx < FAST_LIMIT);
     if (eacc) atomicAdd(&L.tot[2][lane & 15], eacc);
   }
