@@ -38,18 +38,35 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
 }
 
 // One thread per molecule: linear cell and arrival rank within the cell.
+// Consecutive molecules often share a cell (lattice order, or an MD state
+// that started from one), and atomics of a wave to one address are
+// serialised: each run of equal cells in consecutive lanes takes one atomic,
+// by its first lane, which reserves the run's length; the run's lanes take
+// the ranks that follow the returned count in lane order.
 __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ pos, int32_t n, BinArgs g,
                                                    int32_t* __restrict__ cell_of, int32_t* __restrict__ rank,
                                                    int32_t* __restrict__ count) {
-  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double w;
-  int cx = cell_coord(pos[3 * (int64_t)i + 0], g.box[0], g.inv[0], g.n[0], &w);
-  int cy = cell_coord(pos[3 * (int64_t)i + 1], g.box[1], g.inv[1], g.n[1], &w);
-  int cz = cell_coord(pos[3 * (int64_t)i + 2], g.box[2], g.inv[2], g.n[2], &w);
-  int32_t c = (cz * g.n[1] + cy) * g.n[0] + cx;
-  cell_of[i] = c;
-  rank[i] = atomicAdd(&count[c], 1);
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int32_t c = -1;  // lanes past n form runs of their own and add nothing
+  if (i < n) {
+    double w;
+    const int cx = cell_coord(pos[3 * (int64_t)i + 0], g.box[0], g.inv[0], g.n[0], &w);
+    const int cy = cell_coord(pos[3 * (int64_t)i + 1], g.box[1], g.inv[1], g.n[1], &w);
+    const int cz = cell_coord(pos[3 * (int64_t)i + 2], g.box[2], g.inv[2], g.n[2], &w);
+    c = (cz * g.n[1] + cy) * g.n[0] + cx;
+    cell_of[i] = c;
+  }
+  const int32_t prev = __shfl_up(c, 1);
+  const unsigned long long heads = __ballot(lane == 0 || c != prev);
+  const unsigned long long upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 for lane 63)
+  const int head = 63 - __clzll(heads & upto);          // first lane of this lane's run
+  const unsigned long long later = heads & ~upto;
+  const int next = later ? __ffsll((long long)later) - 1 : 64;  // first lane of the next run
+  int32_t base = 0;
+  if (c >= 0 && lane == head) base = atomicAdd(&count[c], next - lane);
+  base = __shfl(base, head);
+  if (c >= 0) rank[i] = base + (lane - head);
 }
 
 // Exclusive prefix over the cell counts in three steps: each workgroup scans

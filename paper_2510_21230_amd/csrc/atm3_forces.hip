@@ -160,21 +160,29 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
   return (long long)lane63(wave_incl_scan64((u64)v));
 }
 
-__device__ __forceinline__ int64_t comb2(int64_t n) { return n * (n - 1) / 2; }
-__device__ __forceinline__ int64_t comb3(int64_t n) { return n * (n - 1) * (n - 2) / 6; }
+__device__ __forceinline__ double comb2(double n) { return n * (n - 1.0) * 0.5; }
+__device__ __forceinline__ double comb3(double n) { return n * (n - 1.0) * (n - 2.0) / 6.0; }
 
 // Molecule triplets of the cell sets a base cell visits (3c08), from the
 // populations N[o] of its eight corner cells: eq. (celltriplet) for the base
 // cell, eq. (twoonetriplets) for the 13 cell pairs and eq. (carttriplets) for
 // the 44 cell triples whose componentwise minimum is the base (corner codes
-// with AND == 0).
-__device__ int64_t candidates_3c08(const int32_t* N) {
-  int64_t t = comb3(N[0]);
+// with AND == 0).  In FP64: every term and partial sum is an integer below
+// 2^53 for populations up to 2^15 per cell (blocks of more than 512
+// molecules are an error of the evaluation anyway), so the count is exact.
+__device__ double candidates_3c08(const int32_t* N) {
+  double n[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) n[o] = (double)N[o];
+  double t = comb3(n[0]);
+#pragma unroll
   for (int p = 0; p < 8; ++p)
+#pragma unroll
     for (int q = p + 1; q < 8; ++q) {
-      if ((p & q) == 0) t += (int64_t)N[q] * comb2(N[p]) + (int64_t)N[p] * comb2(N[q]);
+      if ((p & q) == 0) t += n[q] * comb2(n[p]) + n[p] * comb2(n[q]);
+#pragma unroll
       for (int r = q + 1; r < 8; ++r)
-        if ((p & q & r) == 0) t += (int64_t)N[p] * N[q] * N[r];
+        if ((p & q & r) == 0) t += n[p] * n[q] * n[r];
     }
   return t;
 }
@@ -1269,7 +1277,7 @@ struct Red1Args {
   RedPart* part;
 };
 
-__device__ int64_t candidates_of(const Red1Args& a, int b) {
+__device__ double candidates_of(const Red1Args& a, int b) {
   const int bx = b % a.nx, by = (b / a.nx) % a.ny, bz = b / (a.nx * a.ny);
   int32_t N[8];
   for (int o = 0; o < 8; ++o) {
@@ -1283,18 +1291,21 @@ __device__ int64_t candidates_of(const Red1Args& a, int b) {
   return candidates_3c08(N);
 }
 
-__global__ __launch_bounds__(256) void k_reduce1(Red1Args ra) {
-  __shared__ double sd[4][4];
-  __shared__ long long sc[2][4];
+// 1,024 threads per workgroup: at 1M molecules (85,184 blocks) each thread
+// takes one block, and 16 waves per CU hide the loads' latency
+constexpr int R1WG = 1024;
+__global__ __launch_bounds__(R1WG) void k_reduce1(Red1Args ra) {
+  __shared__ double sd[4][R1WG / 64];
+  __shared__ long long sc[2][R1WG / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int chunk = (ra.ncells + RBLK - 1) / RBLK;
   const int lo = blockIdx.x * chunk;
   const int hi = lo + chunk < ra.ncells ? lo + chunk : ra.ncells;
   double d[4] = {0, 0, 0, 0};
   long long c[2] = {0, 0};
-  for (int b = lo + tid; b < hi; b += 256) {
+  for (int b = lo + tid; b < hi; b += R1WG) {
     for (int k = 0; k < 3; ++k) d[k] += ra.blkd[3 * (int64_t)b + k];
-    d[3] += (double)candidates_of(ra, b);
+    d[3] += candidates_of(ra, b);
     c[0] += ra.blki[2 * (int64_t)b + 0];
     c[1] += ra.blki[2 * (int64_t)b + 1];
   }
@@ -1309,8 +1320,16 @@ __global__ __launch_bounds__(256) void k_reduce1(Red1Args ra) {
   __syncthreads();
   if (tid == 0) {
     RedPart r;
-    for (int k = 0; k < 4; ++k) r.d[k] = sd[k][0] + sd[k][1] + sd[k][2] + sd[k][3];
-    for (int k = 0; k < 2; ++k) r.c[k] = sc[k][0] + sc[k][1] + sc[k][2] + sc[k][3];
+    for (int k = 0; k < 4; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < R1WG / 64; ++w) t += sd[k][w];
+      r.d[k] = t;
+    }
+    for (int k = 0; k < 2; ++k) {
+      long long t = 0;
+      for (int w = 0; w < R1WG / 64; ++w) t += sc[k][w];
+      r.c[k] = t;
+    }
     ra.part[blockIdx.x] = r;
   }
 }
@@ -1451,7 +1470,7 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   r1.nz = a.nz;
   r1.ncells = a.ncells;
   r1.part = part;
-  hipLaunchKernelGGL(k_reduce1, dim3(RBLK), dim3(256), 0, st, r1);
+  hipLaunchKernelGGL(k_reduce1, dim3(RBLK), dim3(R1WG), 0, st, r1);
   ReduceArgs r;
   r.part = part;
   r.defer = a.defer;
