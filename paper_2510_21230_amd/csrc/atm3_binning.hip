@@ -131,6 +131,32 @@ __global__ __launch_bounds__(256) void k_scan_add(int32_t* __restrict__ start, c
   if (c == 0) start[ncells] = tile_sum[ntiles];
 }
 
+// The last two steps in one launch, for at most SCAN_SUMS_MAX tiles:
+// workgroup t adds the sum of the tile sums before tile t (each thread sums
+// a strided share in a fixed order, then the waves, then the workgroup) to
+// the tile's 1,024 prefixes; the last workgroup also writes the total.
+constexpr int SCAN_SUMS_MAX = 4096;
+__global__ __launch_bounds__(256) void k_scan_fix(int32_t* __restrict__ start, const int32_t* __restrict__ tile_sum,
+                                                  int64_t ncells, int32_t ntiles) {
+  __shared__ int32_t ws[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = blockIdx.x;
+  const bool last = t == ntiles - 1;
+  const int upto = last ? ntiles : t;  // the last tile also needs its own sum
+  int v = 0;
+  for (int q = tid; q < upto; q += 256) v += tile_sum[q];
+  const int w = __shfl(wave_incl_scan(v, lane), 63);
+  if (lane == 0) ws[wave] = w;
+  __syncthreads();
+  const int all = ws[0] + ws[1] + ws[2] + ws[3];
+  const int off = last ? all - tile_sum[t] : all;
+  const int64_t c0 = (int64_t)t * TILE + 4 * tid;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (c0 + k < ncells) start[c0 + k] += off;
+  if (last && tid == 0) start[ncells] = all;
+}
+
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ cell_of, const int32_t* __restrict__ rank,
                                                  const int32_t* __restrict__ start, int32_t n,
                                                  int32_t* __restrict__ perm) {
@@ -219,10 +245,7 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
   hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, nn, g, cell_of, rank, count);
   const int32_t ntiles = (int32_t)((gr.ncells + TILE - 1) / TILE);
   int32_t* tile_sum = (int32_t*)ctx->buf[B_TILE];
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(256), 0, st, count, start, tile_sum, gr.ncells);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
-  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, tile_sum, gr.ncells,
-                     ntiles);
+  if ((e = launch_scan(st, count, start, gr.ncells, tile_sum)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, cell_of, rank, start, nn, perm);
   hipLaunchKernelGGL(k_cellsort, dim3(blocks_for(gr.ncells, 256)), dim3(256), 0, st, start, gr.ncells, perm);
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, pos, perm, nn, g, sorted);
@@ -234,8 +257,13 @@ hipError_t launch_binning(atm3_ctx* ctx, const double* pos, int64_t n, const Gri
 hipError_t launch_scan(hipStream_t st, const int32_t* count, int32_t* start, int64_t n, int32_t* tile_sum) {
   const int32_t ntiles = (int32_t)((n + TILE - 1) / TILE);
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles > 0 ? ntiles : 1), dim3(256), 0, st, count, start, tile_sum, n);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
-  hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256), 0, st, start, tile_sum, n, ntiles);
+  if (ntiles >= 1 && ntiles <= SCAN_SUMS_MAX) {
+    hipLaunchKernelGGL(k_scan_fix, dim3(ntiles), dim3(256), 0, st, start, tile_sum, n, ntiles);
+  } else {
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, st, tile_sum, ntiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256), 0, st, start, tile_sum, n,
+                       ntiles);
+  }
   return hipGetLastError();
 }
 

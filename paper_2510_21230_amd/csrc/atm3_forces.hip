@@ -401,6 +401,8 @@ struct FmArgs {
   double box[3];
   float lo2, hi2;
   double rc2;
+  int32_t* defer;  // the hand-on queues, emptied here for the block kernels
+  int32_t ncells;
 };
 
 __global__ __launch_bounds__(256) void k_fmask(FmArgs a) {
@@ -408,6 +410,11 @@ __global__ __launch_bounds__(256) void k_fmask(FmArgs a) {
   __shared__ int32_t cst[FM_CELLS + 1];  // staged start of each staged cell
   __shared__ int32_t cgs[FM_CELLS];      // sorted start of each staged cell
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) {  // queue counts and status (the block kernels run after this launch)
+    a.defer[0] = 0;
+    a.defer[1] = ATM3_OK;
+    a.defer[2 + a.ncells] = 0;
+  }
   const int nseg = (a.nx + FM_G - 1) / FM_G;
   const int g = blockIdx.x;
   const int seg = g % nseg, y = (g / nseg) % a.ny, z = g / (nseg * a.ny);
@@ -1235,14 +1242,6 @@ __global__ __launch_bounds__(WG) void k_block_big(ForceArgs a) {
   }
 }
 
-__global__ void k_reset(int32_t* defer, int32_t ncells) {
-  if (threadIdx.x == 0) {
-    defer[0] = 0;
-    defer[1] = ATM3_OK;
-    defer[2 + ncells] = 0;
-  }
-}
-
 // Sum the eight corner partials of each molecule (exact, fixed point) and
 // write the force in input order.
 __global__ __launch_bounds__(256) void k_finalize(const u64* __restrict__ fpart, const int32_t* __restrict__ perm,
@@ -1419,7 +1418,6 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   a.k15nu = (float)(1.875 * p.nu);
   a.k075nu = (float)(0.75 * p.nu);
 
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, a.defer, a.ncells);
   const int per = (a.ncells + 7) / 8;
   FmArgs fa;
   fa.sorted = a.sorted;
@@ -1437,6 +1435,8 @@ hipError_t launch_forces(atm3_ctx* ctx, const double* pos, int64_t n, const Grid
   fa.lo2 = a.lo2;
   fa.hi2 = a.hi2;
   fa.rc2 = a.rc2;
+  fa.defer = a.defer;
+  fa.ncells = a.ncells;
   a.fmask = fa.fmask;
   a.fm_ok = fa.fm_ok;
   // the queued wide tier loops over the queue; its LDS (about 67 KB) admits
