@@ -71,10 +71,24 @@ def _binning_cases():
     xs = np.array([0.0, 2.5, np.nextafter(2.5, 0), 10.0, -0.1, -1e-300, np.nextafter(10.0, 0), 25.0, 7.5, -10.0])
     p3 = np.stack([xs, xs[::-1], np.roll(xs, 3)], axis=1)
     p3 = np.concatenate([p3, workloads.uniform(50, [L, L, L], seed=42)[0]])
-    return [("fcc1k", p1, b1), ("ortho", p2, b2), ("edges", p3, np.array([L, L, L]))]
+    # runs of equal cells in consecutive molecules, of random lengths (1-90),
+    # across wave boundaries, N not a multiple of 64
+    rng = np.random.default_rng(43)
+    b4 = np.array([20.0, 15.0, 12.5])
+    lens = rng.integers(1, 91, 120)
+    anchors = rng.uniform(0.0, 1.0, (len(lens), 3)) * b4
+    p4 = np.concatenate([a + rng.uniform(-0.3, 0.3, (m, 3)) for a, m in zip(anchors, lens)])
+    # cell-count scans of exactly 4,096 tiles of 1,024 cells (256 x 128 x 128
+    # cells) and of more (162^3 cells: the separate scan of the tile totals)
+    b5 = np.array([640.0, 320.0, 320.0])
+    p5 = workloads.uniform(20000, b5, seed=44)[0]
+    b6 = np.array([405.0, 405.0, 405.0])
+    p6 = workloads.uniform(20000, b6, seed=45)[0]
+    return [("fcc1k", p1, b1), ("ortho", p2, b2), ("edges", p3, np.array([L, L, L])), ("runs", p4, b4),
+            ("tiles4096", p5, b5), ("tiles4152", p6, b6)]
 
 
-@pytest.mark.parametrize("case", range(3))
+@pytest.mark.parametrize("case", range(6))
 def test_binning_bit_exact(torch_cuda, orc, case):
     import paper_2510_21230_amd as atm3
     name, pos, box = _binning_cases()[case]
