@@ -1199,15 +1199,36 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         if (p % PF_NCLS) atomicAdd(&L.ccnt[tid >> 7][p % PF_NCLS], 1);
       }
     };
-    // class cursors, largest items first: both halves (sub < 0) or one
-    auto set_cursors = [&](int sub) {
-      if (tid == 0) {
-        int run = 0;
-        for (int c = PF_NCLS; c >= 1; --c) {
-          L.cursor[c] = run;
-          run += sub < 0 ? L.ccnt[0][c] + L.ccnt[1][c] : L.ccnt[sub][c];
+    // class cursors, largest items first, by wave 0 (lane l takes class
+    // PF_NCLS - l, a scan gives the cursors): both halves (sub < 0) or one.
+    // With `decide`, the round's class totals first choose one pass (both
+    // halves, if their items fit KCAP together) or two (sub 0 now), and
+    // flag the block when one half alone overflows
+    auto wave_incl = [&](int v) {
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+      }
+      return v;
+    };
+    auto set_cursors = [&](int sub, bool decide) {
+      if (wave == 0) {
+        const int c = PF_NCLS - lane;
+        const int c0 = lane < PF_NCLS ? L.ccnt[0][c] : 0, c1 = lane < PF_NCLS ? L.ccnt[1][c] : 0;
+        if (decide) {
+          const int t0 = __shfl(wave_incl(c0), 63), t1 = __shfl(wave_incl(c1), 63);
+          const int nsub = (t0 + t1 <= KCAP) ? 1 : 2;
+          if (lane == 0) {
+            L.nsub = nsub;
+            if (t0 > KCAP || t1 > KCAP) L.abort = 1;
+          }
+          sub = nsub == 1 ? -1 : 0;
         }
-        L.nitems = run;
+        const int v = sub < 0 ? c0 + c1 : (sub == 0 ? c0 : c1);
+        const int incl = wave_incl(v);
+        if (lane < PF_NCLS) L.cursor[c] = incl - v;
+        if (lane == PF_NCLS - 1) L.nitems = incl;
       }
     };
     // this thread's items: runs of PF_NCLS set bits, lowest first, then the rest
@@ -1331,29 +1352,19 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       // of the workgroup's rows one after the other, the second half forming
       // its K words again (the block is handed on only if one half alone
       // overflows)
-      if (tid == 0) {
-        int t0 = 0, t1 = 0;
-        for (int c = 1; c <= PF_NCLS; ++c) {
-          t0 += L.ccnt[0][c];
-          t1 += L.ccnt[1][c];
-        }
-        L.nsub = (t0 + t1 <= KCAP) ? 1 : 2;
-        if (t0 > KCAP || t1 > KCAP) L.abort = 1;
-      }
+      set_cursors(0, true);
       __syncthreads();
       if (L.abort) {
         fits = false;
         break;
       }
       const int nsub = L.nsub;
-      set_cursors(nsub == 1 ? -1 : 0);
-      __syncthreads();
       if (nsub == 1 || (tid >> 7) == 0) place_items(r0, K);
       __syncthreads();
       atm_pass();
       __syncthreads();
       if (nsub == 2) {
-        set_cursors(1);
+        set_cursors(1, false);
         __syncthreads();
         if ((tid >> 7) == 1) {
 #pragma unroll
