@@ -888,7 +888,7 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
 // those with y = |r_ik|^2 >= x, z = |r_jk|^2 >= x and x y z < rc^6.
 // Shells: every staged squared distance D falls in one of 16 shells, shell
 // 0 below t1 = rc^2 (1 + 1e-4) / 8 and shell a >= 1 from t1 2^((a - 1) / 2)
-// up (read off the FP32 exponent and mantissa of D / t1), held as four bit
+// up (one more than the FP32 exponent of (D / t1)^2), held as four bit
 // planes per row and mask word.  A lane per row keeps the k whose shells
 // with i and with j are both at least x's and whose shell lower bounds allow
 // x y z < rc^6 (1 + 1e-3): with y >= t1 2^((a - 1) / 2) and z likewise that
@@ -906,7 +906,6 @@ __global__ __launch_bounds__(64 * PB_WAVES) void k_prod_block(ProdArgs a) {
 constexpr int PF_WG = 256;
 constexpr int PF_NCLS = 12;                    // third molecules per work item at most
 constexpr int PF_NSH = 16;                     // shells: four bit planes
-constexpr uint32_t PF_SQRT2_MANT = 0x3504F3u;  // mantissa bits of sqrt(2) in FP32
 constexpr float PF_FIX_LIMIT = 262144.f;       // 2^18: the fixed-point conversion's range
 
 template <int NW, int PCAP, int KCAP>
@@ -940,12 +939,14 @@ __device__ __forceinline__ unsigned long long pf_fixd(double v) {
   return (unsigned long long)__double_as_longlong(t) - 0x4138000000000000ull;
 }
 
-// Shell of a squared distance d (inv_t1 = 1 / t1).
+// Shell of a squared distance d (inv_t1 = 1 / t1): shell a >= 1 holds
+// t1 2^((a - 1) / 2) <= d, that is 2^(a - 1) <= (d / t1)^2, so a is one more
+// than the binary exponent of (d / t1)^2 (in FP32, a monotone function of
+// d); 0 below t1, at most PF_NSH - 1.
 __device__ __forceinline__ int pf_shell(float d, float inv_t1) {
   const float u = d * inv_t1;
-  const uint32_t bits = __float_as_uint(u);
-  const int s = 1 + 2 * ((int)(bits >> 23) - 127) + ((bits & 0x7fffffu) >= PF_SQRT2_MANT ? 1 : 0);
-  return u < 1.f ? 0 : (s > PF_NSH - 1 ? PF_NSH - 1 : s);
+  const int e = (int)(__float_as_uint(u * u) >> 23) - 126;
+  return min(max(e, 0), PF_NSH - 1);
 }
 
 // Bit-sliced comparisons with a per-lane constant c whose bits are given as
@@ -1064,20 +1065,23 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
     }
     for (int t = tid; t < n; t += PF_WG) L.f[0][t] = L.f[1][t] = L.f[2][t] = 0ull;
     __syncthreads();
-    // 2. shell planes, a wave per (row, word), and the ownership masks
-    for (int task = wave; task < n * NW; task += PF_WG / 64) {
-      const int i = task / NW, w = task - (task / NW) * NW;
+    // 2. shell planes, a wave per row (all its words), and the ownership masks
+    for (int i = wave; i < n; i += PF_WG / 64) {
       const float4 pi = L.p[i];
-      const int k = 64 * w + lane;
-      int s = 0;
-      if (k < n) {
-        const float4 pk = L.p[k];
-        s = pf_shell(sq3(make_float3(pi.x - pk.x, pi.y - pk.y, pi.z - pk.z)), a.pf_inv_t1);
-      }
-      const unsigned long long b0 = __ballot(s & 1), b1 = __ballot(s & 2), b2 = __ballot(s & 4), b3 = __ballot(s & 8);
-      if (lane == 0) {
-        *(ulonglong2*)&L.pl[i][w][0] = make_ulonglong2(b0, b1);
-        *(ulonglong2*)&L.pl[i][w][2] = make_ulonglong2(b2, b3);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const int k = 64 * w + lane;
+        int s = 0;
+        if (k < n) {
+          const float4 pk = L.p[k];
+          s = pf_shell(sq3(make_float3(pi.x - pk.x, pi.y - pk.y, pi.z - pk.z)), a.pf_inv_t1);
+        }
+        const unsigned long long b0 = __ballot(s & 1), b1 = __ballot(s & 2), b2 = __ballot(s & 4),
+                                 b3 = __ballot(s & 8);
+        if (lane == 0) {
+          *(ulonglong2*)&L.pl[i][w][0] = make_ulonglong2(b0, b1);
+          *(ulonglong2*)&L.pl[i][w][2] = make_ulonglong2(b2, b3);
+        }
       }
     }
     constexpr int NOWN = (VAR == ATM3_VARIANT_3C08) ? 8 : 2;
