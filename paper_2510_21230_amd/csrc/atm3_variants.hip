@@ -994,10 +994,16 @@ __device__ __forceinline__ int pf_scan(int v, int32_t* wsum, int* total) {
   return before + s - v;
 }
 
-// RPT rows per thread and round: a round's items must fit KCAP (on the
-// benchmark fluid at most about 1,600 of 2,048 for 3c08 with 512 rows, and
-// 1,300 of 1,536 for 3c18 with 256: its first rows, those of base-cell
-// molecules, take third molecules from the whole set)
+// RPT rows per thread and round.  A round whose items exceed KCAP runs as
+// two halves; a half that alone exceeds it hands the block on.  On the
+// benchmark fluid 3c08 takes rounds of 512 rows (at most about 1,600 of
+// 2,048 items).  3c18 takes rounds of 1,024: its first rows, those of the
+// base cell's molecules, take third molecules from the whole set and split
+// into halves, but most of its rows have no base-cell member, must take
+// the third molecule from the base cell, and make items of one or two
+// candidates; small rounds of those were dominated by their barriers
+// (rounds of 256 rows: 16.3 ms per evaluation, 512: 15.2, 1,024: 14.8;
+// 1,536 and more hand sets on)
 template <int VAR, int NW, int PCAP, int KCAP, int RPT>
 __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
   using Lds = ProdFastLds<NW, PCAP, KCAP>;
@@ -1816,7 +1822,7 @@ hipError_t launch_onesided(atm3_ctx* ctx, const double* pos, int64_t n, const Gr
       else if (p.variant == ATM3_VARIANT_3C08)
         hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C08, 2, 2048, 2048, 2>), dim3(grid), dim3(PF_WG), 0, st, b);
       else
-        hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C18, 3, 4096, 1536, 1>), dim3(grid), dim3(PF_WG), 0, st, b);
+        hipLaunchKernelGGL((k_prod_fast<ATM3_VARIANT_3C18, 3, 4096, 1536, 4>), dim3(grid), dim3(PF_WG), 0, st, b);
     }
     b.dpart = dpart + 4 * (size_t)(nb1 + nbf);
     b.ipart = ipart + 4 * (size_t)(nb1 + nbf);
