@@ -1279,7 +1279,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         const float4 pi = L.p[i], pj = L.p[j];
         const float ijx = pi.x - pj.x, ijy = pi.y - pj.y, ijz = pi.z - pj.z;
         const float x = sq3(make_float3(ijx, ijy, ijz));
-        const float ix = 1.f / x;
+        const float ix = __builtin_amdgcn_rcpf(x);  // 1 ulp, as in the pairwise-cutoff block kernel
         const int kij = (i << 8) | j;
         float cxs = 0.f, fix = 0.f, fiy = 0.f, fiz = 0.f, fjx = 0.f, fjy = 0.f, fjz = 0.f, eu = 0.f;
         int nt = 0;
@@ -1292,10 +1292,14 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           const float y = sq3(make_float3(ikx, iky, ikz)), z = sq3(make_float3(jkx, jky, jkz));
           const int kik = k < i ? ((k << 8) | i) : ((i << 8) | k);
           const int kjk = k < j ? ((k << 8) | j) : ((j << 8) | k);
-          if (!((y > x || (y == x && kik > kij)) && (z > x || (z == x && kjk > kij)))) continue;
+          // designation and product tests as one mask (bitwise, so that they
+          // compile to lane masks, not to a branch per condition); the
+          // oracle's FP64 test runs only for designated candidates in the
+          // band or with a side under a quarter cell
+          const bool des = ((y > x) | ((y == x) & (kik > kij))) & ((z > x) | ((z == x) & (kjk > kij)));
           const float prod = (x * y) * z;
-          bool in = prod < a.lo6f;
-          if ((!in && prod < a.hi6f) || fminf(x, fminf(y, z)) < a.small2) {
+          bool in = des & (prod < a.lo6f);
+          if (des & ((!in & (prod < a.hi6f)) | (fminf(x, fminf(y, z)) < a.small2))) {
             const int oi = __float_as_int(pi.w), oj = __float_as_int(pj.w), ok = __float_as_int(pk.w);
             const double ex = exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]);
             const double ey = exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]);
