@@ -920,7 +920,7 @@ struct ProdFastLds {
   unsigned long long kset[KCAP];         // third molecules of an item (bits of word w)
   uint16_t kmeta[KCAP];                  // row | w << 12
   uint8_t code[MAXB];
-  int32_t cnt[16], base[16], cell[16];
+  int32_t cnt[16], base[16], cell[16], gst[16];  // populations, staged offsets, cells, first sorted slots
   int32_t ccnt[2][PF_NCLS + 1], cursor[PF_NCLS + 1];  // class counts per half of the workgroup
   int32_t wsum[PF_WG / 64];
   int32_t nrows, nitems, abort, nsub;
@@ -1032,7 +1032,8 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
     const int ux = wrapc(bx + dx, a.nx), uy = wrapc(by + dy, a.ny), uz = wrapc(bz + dz, a.nz);
     const int cc = (uz * a.ny + uy) * a.nx + ux;
     L.cell[tid] = cc;
-    L.cnt[tid] = a.start[cc + 1] - a.start[cc];
+    L.gst[tid] = a.start[cc];
+    L.cnt[tid] = a.start[cc + 1] - L.gst[tid];
   }
   if (tid < 2 * (PF_NCLS + 1)) L.ccnt[tid / (PF_NCLS + 1)][tid % (PF_NCLS + 1)] = 0;
   if (tid == 0) L.abort = 0;
@@ -1052,22 +1053,25 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
   double elj = 0.0, wlj = 0.0;
   bool fits = n <= MAXB;
   if (fits) {
-    // 1. stage the cell set (block frame: relative to the base cell's centre)
-    for (int q = wave; q < NCS; q += PF_WG / 64) {
+    // 1. stage the cell set (block frame: relative to the base cell's centre),
+    //    a thread per molecule: its cell q is the number of later cells
+    //    whose staged range starts at or before it, so that every record is
+    //    fetched in one round of independent loads
+    for (int t = tid; t < n; t += PF_WG) {
+      int q = 0;
+#pragma unroll
+      for (int c = 1; c < NCS; ++c) q += (L.base[c] <= t) ? 1 : 0;
       int dx, dy, dz;
       offs(q, dx, dy, dz);
-      const int t0 = a.start[L.cell[q]], m = L.cnt[q], bb = L.base[q];
       const uint8_t code = (VAR == ATM3_VARIANT_3C08) ? (uint8_t)q : (uint8_t)(q == 0 ? 0 : 1);
-      for (int t = lane; t < m; t += 64) {
-        const double4 o = a.sorted[t0 + t];
-        const double vx = o.x + dx * a.side[0], vy = o.y + dy * a.side[1], vz = o.z + dz * a.side[2];
-        const float hx = (float)vx, hy = (float)vy, hz = (float)vz;
-        L.p[bb + t] = make_float4(hx, hy, hz, __int_as_float((int)o.w));
-        L.lo[0][bb + t] = (float)(vx - (double)hx);
-        L.lo[1][bb + t] = (float)(vy - (double)hy);
-        L.lo[2][bb + t] = (float)(vz - (double)hz);
-        L.code[bb + t] = code;
-      }
+      const double4 o = a.sorted[L.gst[q] + (t - L.base[q])];
+      const double vx = o.x + dx * a.side[0], vy = o.y + dy * a.side[1], vz = o.z + dz * a.side[2];
+      const float hx = (float)vx, hy = (float)vy, hz = (float)vz;
+      L.p[t] = make_float4(hx, hy, hz, __int_as_float((int)o.w));
+      L.lo[0][t] = (float)(vx - (double)hx);
+      L.lo[1][t] = (float)(vy - (double)hy);
+      L.lo[2][t] = (float)(vz - (double)hz);
+      L.code[t] = code;
     }
     for (int t = tid; t < n; t += PF_WG) L.f[0][t] = L.f[1][t] = L.f[2][t] = 0ull;
     __syncthreads();
