@@ -1245,30 +1245,41 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         if (lane == PF_NCLS - 1) L.nitems = incl;
       }
     };
-    // this thread's items: runs of PF_NCLS set bits, lowest first, then the rest
+    // this thread's items: runs of PF_NCLS set bits, lowest first, then the
+    // rest.  The slot of the first item of every word (the whole word when
+    // it has at most PF_NCLS bits) comes from an atomic per word, all of
+    // them issued before any is waited for; then the stores, and the further
+    // items of words with more bits
     auto place_items = [&](int r0, unsigned long long (&K)[RPT][NW]) {
+      int slot[RPT][NW];
+#pragma unroll
+      for (int rr = 0; rr < RPT; ++rr)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const int pc = __popcll(K[rr][w]), c = pc < PF_NCLS ? pc : PF_NCLS;
+          slot[rr][w] = c ? atomicAdd(&L.cursor[c], 1) : 0;
+        }
 #pragma unroll
       for (int rr = 0; rr < RPT; ++rr) {
         const int q = r0 + rr * PF_WG + tid;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           unsigned long long bits = K[rr][w];
+          int at = slot[rr][w];
           while (bits) {
             unsigned long long run = bits;
-            int c = __popcll(bits);
-            if (c > PF_NCLS) {
-              run = 0ull;
+            if (__popcll(bits) > PF_NCLS) {  // the lowest PF_NCLS bits
               unsigned long long t = bits;
-              for (int u = 0; u < PF_NCLS; ++u) {
-                run |= t & (~t + 1ull);
-                t &= t - 1ull;
-              }
-              c = PF_NCLS;
+              for (int u = 0; u < PF_NCLS; ++u) t &= t - 1ull;
+              run = bits ^ t;
             }
             bits ^= run;
-            const int slot = atomicAdd(&L.cursor[c], 1);
-            L.kset[slot] = run;
-            L.kmeta[slot] = (uint16_t)(q | (w << 12));
+            L.kset[at] = run;
+            L.kmeta[at] = (uint16_t)(q | (w << 12));
+            if (bits) {
+              const int pc = __popcll(bits);
+              at = atomicAdd(&L.cursor[pc < PF_NCLS ? pc : PF_NCLS], 1);
+            }
           }
         }
       }
