@@ -870,25 +870,50 @@ __device__ bool do_block_fast(const ForceArgs& a, int b, LdsTier<NW, PCAP, KCAP>
     //     + WG r, so that neighbouring lanes hold pairs of different rows,
     //     whose K overlap less: fewer same-address F_k atomics later) cut
     //     into runs and placed at their class cursors
-    for (int r = 0; WG * r < nne; ++r) {
-      const int p = ((tid * 37) & (WG - 1)) + WG * r;
-      if (p >= nne) continue;
-      const int v = L.nelist[p];
-      const int e = L.plist[v & 8191], w = v >> 13;
-      const int i = e & 255, j = e >> 8;
-      u64 K = L.mask[i * NW + w] & L.mask[j * NW + w] & L.allow[(L.scode[i] & L.scode[j]) * NW + w];
-      while (K) {
-        u64 run = K;
-        if (__popcll(K) > NCLS) {  // the lowest NCLS bits
-          u64 x = K;
+    //    Three entries per thread at a time: their K words, then the slots
+    //    of their first items (independent atomics, issued together), then
+    //    the stores and any further items
+    for (int r0 = 0; WG * r0 < nne; r0 += 3) {
+      u64 Kb[3];
+      int vb[3], slot[3];
 #pragma unroll
-          for (int t = 0; t < NCLS; ++t) x &= x - 1ull;
-          run = K ^ x;
+      for (int b = 0; b < 3; ++b) {
+        const int p = ((tid * 37) & (WG - 1)) + WG * (r0 + b);
+        Kb[b] = 0ull;
+        vb[b] = 0;
+        if (p < nne) {
+          const int v = L.nelist[p];
+          const int e = L.plist[v & 8191], w = v >> 13;
+          const int i = e & 255, j = e >> 8;
+          Kb[b] = L.mask[i * NW + w] & L.mask[j * NW + w] & L.allow[(L.scode[i] & L.scode[j]) * NW + w];
+          vb[b] = v;
         }
-        K ^= run;
-        const int slot = atomicAdd(&L.cursor[__popcll(run)], 1);
-        L.kset[slot] = run;
-        L.kmeta[slot] = (uint16_t)v;
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int pc = __popcll(Kb[b]), c = pc < NCLS ? pc : NCLS;
+        slot[b] = c ? atomicAdd(&L.cursor[c], 1) : 0;
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        u64 K = Kb[b];
+        int at = slot[b];
+        while (K) {
+          u64 run = K;
+          if (__popcll(K) > NCLS) {  // the lowest NCLS bits
+            u64 x = K;
+#pragma unroll
+            for (int t = 0; t < NCLS; ++t) x &= x - 1ull;
+            run = K ^ x;
+          }
+          K ^= run;
+          L.kset[at] = run;
+          L.kmeta[at] = (uint16_t)vb[b];
+          if (K) {
+            const int pc = __popcll(K);
+            at = atomicAdd(&L.cursor[pc < NCLS ? pc : NCLS], 1);
+          }
+        }
       }
     }
     __syncthreads();
