@@ -1075,11 +1075,16 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
     }
     for (int t = tid; t < n; t += PF_WG) L.f[0][t] = L.f[1][t] = L.f[2][t] = 0ull;
     __syncthreads();
-    // 2. shell planes, a wave per row (all its words), and the ownership masks
+    // 2. shell planes, a wave per row, and the ownership masks.  shell(i, k)
+    //    equals shell(k, i) bit for bit (the FP32 differences are exact
+    //    negatives of each other and sq3 sums in a fixed order), so row i
+    //    computes its words w >= i / 64 only; the words below the diagonal of
+    //    64 x 64 blocks are bit transposes of the blocks above, next
     for (int i = wave; i < n; i += PF_WG / 64) {
       const float4 pi = L.p[i];
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
+        if (w < (i >> 6)) continue;  // uniform: one row per wave
         const int k = 64 * w + lane;
         int s = 0;
         if (k < n) {
@@ -1102,6 +1107,37 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       if (k < n) okk = (VAR == ATM3_VARIANT_3C08) ? (L.code[k] & m) == 0 : (m == 1 || L.code[k] == 0);
       const unsigned long long bits = __ballot(okk);
       if (lane == 0) L.own[m][w] = bits;
+    }
+    __syncthreads();
+    // block (I, K), K > I, plane b: lane l holds row 64 I + l's word K (zero
+    // past n); six butterfly stages (lanes l and l ^ h exchange their words,
+    // h = 32 ... 1, and each keeps its own bit groups of size h on its side
+    // of the diagonal and takes the partner's from the other) leave in lane
+    // l the column 64 K + l over those rows, which is row 64 K + l's word I
+    {
+      constexpr int NBLK = NW * (NW - 1) / 2;
+      for (int task = wave; task < 4 * NBLK; task += PF_WG / 64) {
+        const int blk = task >> 2, b = task & 3;
+        int I = 0, t = blk;  // the blk-th pair I < K in order
+        while (t >= NW - 1 - I) t -= NW - 1 - I++;
+        const int K = I + 1 + t;
+        if (64 * K >= n) continue;  // uniform: no rows in word K
+        const int r = 64 * I + lane;
+        unsigned long long x = r < n ? L.pl[r][K][b] : 0ull;
+#pragma unroll
+        for (int st = 5; st >= 0; --st) {
+          const int h = 1 << st;
+          const unsigned long long m = h == 32 ? 0x00000000FFFFFFFFull
+                                     : h == 16 ? 0x0000FFFF0000FFFFull
+                                     : h == 8  ? 0x00FF00FF00FF00FFull
+                                     : h == 4  ? 0x0F0F0F0F0F0F0F0Full
+                                     : h == 2  ? 0x3333333333333333ull
+                                               : 0x5555555555555555ull;
+          const unsigned long long y = __shfl_xor(x, h);
+          x = (lane & h) ? ((x & ~m) | ((y & ~m) >> h)) : ((x & m) | ((y & m) << h));
+        }
+        L.pl[64 * K + lane][I][b] = x;
+      }
     }
     __syncthreads();
     // 3. rows: pairs i < j with shell <= 6 (D < t1 * 8 = rc^2 (1 + 1e-4)), a thread per molecule i
