@@ -69,9 +69,11 @@ __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ po
   if (c >= 0) rank[i] = base + (lane - head);
 }
 
-// Exclusive prefix over the cell counts in three steps: each workgroup scans
-// a tile of 1024 cells (4 consecutive cells per thread) and records the tile
-// sum; one workgroup scans the tile sums; the tile offsets are added.
+// Exclusive prefix over the cell counts: each workgroup scans a tile of 1024
+// cells (4 consecutive cells per thread) and records the tile sum; then
+// either each tile's workgroup sums the tile sums before it and adds them
+// (k_scan_fix, up to SCAN_SUMS_MAX tiles), or one workgroup scans the tile
+// sums and a third launch adds the tile offsets.
 constexpr int TILE = 1024;
 
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
