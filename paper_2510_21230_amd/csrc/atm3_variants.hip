@@ -546,9 +546,9 @@ struct ProdArgs {
   double rc2;
   float lo2f, hi2f;
   double* tpart;
-  // shell-pruned tier: 1 / t1, t1^2 and rc^6 (1 + 1e-3); per base cell, 1 if
-  // k_prod_fast handed the cell on (k_prod_block skips the others)
-  float pf_inv_t1, pf_t1sq, pf_h6;
+  // shell-pruned tier: 1 / t1 and log2(rc^6 (1 + 1e-3) / t1^2); per base
+  // cell, 1 if k_prod_fast handed the cell on (k_prod_block skips the others)
+  float pf_inv_t1, pf_lh;
   int32_t* pdefer;
   // with pdefer: the LJ pairs the cell set owns (Newton 3, fixed point), as
   // the one-sided kernel is not run then
@@ -1182,7 +1182,9 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
       const float x = sq3(make_float3(pi.x - pj.x, pi.y - pj.y, pi.z - pj.z));
       const int ax = pf_shell(x, a.pf_inv_t1);
       int cmax = 31;
-      if (ax > 0) cmax = min(31, (int)ceilf(2.f * __log2f(a.pf_h6 / (a.pf_t1sq * x)) + 1e-3f) + 1);
+      // 2 log2(rc^6 (1 + 1e-3) / (t1^2 x)) from a constant and log2 x; the
+      // 1e-3 added before rounding up covers the rounding of both forms
+      if (ax > 0) cmax = min(31, (int)ceilf(2.f * (a.pf_lh - __log2f(x)) + 1e-3f) + 1);
       unsigned long long mx[4], mc[5];
 #pragma unroll
       for (int t = 0; t < 4; ++t) mx[t] = ((ax >> t) & 1) ? ~0ull : 0ull;
@@ -1234,7 +1236,9 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           c = (vi[t] & vj[t]) | (c & h);
         }
         s[4] = c;
-        unsigned long long kw = pf_ge<4>(vi, mx) & pf_ge<4>(vj, mx) & pf_le<5>(s, mc) & ow;
+        // shells >= ax: the row's own shell is at most 6, so the top plane
+        // alone decides shells of 8 and more, three planes the others
+        unsigned long long kw = (vi[3] | pf_ge<3>(vi, mx)) & (vj[3] | pf_ge<3>(vj, mx)) & pf_le<5>(s, mc) & ow;
         if ((i >> 6) == w) kw &= ~(1ull << (i & 63));
         if ((j >> 6) == w) kw &= ~(1ull << (j & 63));
         Kq[w] = kw;
@@ -1711,8 +1715,7 @@ ProdArgs prod_args(const OneArgs& a, const Grid& g, int variant, int splits, uns
   b.tpart = nullptr;
   const double t1 = a.rc2 * (1.0 + 1e-4) / 8.0;
   b.pf_inv_t1 = (float)(1.0 / t1);
-  b.pf_t1sq = (float)(t1 * t1);
-  b.pf_h6 = (float)(a.rc6 * (1.0 + 1e-3));
+  b.pf_lh = (float)std::log2(a.rc6 * (1.0 + 1e-3) / (t1 * t1));
   b.pdefer = nullptr;
   b.lj = 0;
   b.sig2 = a.sig2;
