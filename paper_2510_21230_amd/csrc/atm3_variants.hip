@@ -1345,13 +1345,17 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           const float ikx = pi.x - pk.x, iky = pi.y - pk.y, ikz = pi.z - pk.z;
           const float jkx = pj.x - pk.x, jky = pj.y - pk.y, jkz = pj.z - pk.z;
           const float y = sq3(make_float3(ikx, iky, ikz)), z = sq3(make_float3(jkx, jky, jkz));
-          const int kik = k < i ? ((k << 8) | i) : ((i << 8) | k);
-          const int kjk = k < j ? ((k << 8) | j) : ((j << 8) | k);
           // designation and product tests as one mask (bitwise, so that they
-          // compile to lane masks, not to a branch per condition); the
-          // oracle's FP64 test runs only for designated candidates in the
-          // band or with a side under a quarter cell
-          const bool des = ((y > x) | ((y == x) & (kik > kij))) & ((z > x) | ((z == x) & (kjk > kij)));
+          // compile to lane masks, not to a branch per condition); the pair
+          // keys break ties of squared sides only, which a wave almost never
+          // has; the oracle's FP64 test runs only for designated candidates
+          // in the band or with a side under a quarter cell
+          bool des = (y > x) & (z > x);
+          if ((y == x) | (z == x)) {
+            const int kik = k < i ? ((k << 8) | i) : ((i << 8) | k);
+            const int kjk = k < j ? ((k << 8) | j) : ((j << 8) | k);
+            des = ((y > x) | ((y == x) & (kik > kij))) & ((z > x) | ((z == x) & (kjk > kij)));
+          }
           const float prod = (x * y) * z;
           bool in = des & (prod < a.lo6f);
           if (des & ((!in & (prod < a.hi6f)) | (fminf(x, fminf(y, z)) < a.small2))) {
