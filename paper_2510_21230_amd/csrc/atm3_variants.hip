@@ -1336,6 +1336,9 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
         const float x = sq3(make_float3(ijx, ijy, ijz));
         const float ix = __builtin_amdgcn_rcpf(x);  // 1 ulp, as in the pairwise-cutoff block kernel
         const int kij = (i << 8) | j;
+        // a designated candidate has x as its shortest side, so the
+        // quarter-cell test of the oracle's FP64 path reads x alone
+        const bool xsmall = x < a.small2;
         float cxs = 0.f, fix = 0.f, fiy = 0.f, fiz = 0.f, fjx = 0.f, fjy = 0.f, fjz = 0.f, eu = 0.f;
         int nt = 0;
         while (bits) {
@@ -1358,7 +1361,7 @@ __global__ __launch_bounds__(PF_WG) void k_prod_fast(ProdArgs a) {
           }
           const float prod = (x * y) * z;
           bool in = des & (prod < a.lo6f);
-          if (des & ((!in & (prod < a.hi6f)) | (fminf(x, fminf(y, z)) < a.small2))) {
+          if (des & ((!in & (prod < a.hi6f)) | xsmall)) {
             const int oi = __float_as_int(pi.w), oj = __float_as_int(pj.w), ok = __float_as_int(pk.w);
             const double ex = exact_r2(a.pos, oi, oj, a.box[0], a.box[1], a.box[2]);
             const double ey = exact_r2(a.pos, oi, ok, a.box[0], a.box[1], a.box[2]);
